@@ -1,0 +1,169 @@
+"""Generating vectors for the rank-1 lattice rule (Section III, Eq. 17).
+
+The lattice points are x_i = {i z / n}; the rule needs an integer vector z
+whose components are coprime to n.  The paper mentions the
+component-by-component construction without parameters, so this module
+builds Korobov vectors z = (1, a, a^2, ..., a^(d-1)) mod n and picks the
+multiplier a among a fixed, seeded candidate set by the worst-case error
+criterion P_2 of the weighted Korobov space with unit weights (Dick, Kuo
+and Sloan, Acta Numerica 22 (2013), Section 5):
+
+    P_2(z) = -1 + (1/n) sum_i prod_j (1 + 2 pi^2 B_2({i z_j / n})),
+    B_2(x) = x^2 - x + 1/6.
+
+The search is expensive for large n, so the vectors are generated once by
+``python -m seeded_inputs.lattice`` and stored in ``lattices.json`` beside
+this file; both the oracle and the GPU path read that file.  The vectors
+are inputs of the method, not part of its arithmetic.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+from functools import lru_cache
+
+import numpy as np
+
+from .rng import splitmix64
+
+DMAX = 8               # every stored vector has this many components
+SEARCH_DIM = 6         # P_2 is minimised for the largest sector dimension used
+_DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lattices.json")
+
+# Lattice sizes used by the tests and workloads.  Primes for the plain
+# shifted rules; powers of two for the embedded (doubling) rules.
+PRIME_SIZES = [1009, 4099, 10007, 65521, 100003, 131071, 262139, 524287,
+               1000003, 1048573, 2097143, 4194301, 8388593, 10000019,
+               16777213, 33554393, 67108859, 100000007]
+POW2_SIZES = [1 << k for k in range(10, 27)]
+
+
+def is_prime(n: int) -> bool:
+    if n < 2:
+        return False
+    small = (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37)
+    for p in small:
+        if n % p == 0:
+            return n == p
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for a in small:          # deterministic for n < 3.3e24
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def korobov_vector(n: int, a: int, dim: int = DMAX) -> list[int]:
+    z, p = [], 1
+    for _ in range(dim):
+        z.append(p % n)
+        p = p * a % n
+    return z
+
+
+def p2_criterion(n: int, z, chunk: int = 1 << 21) -> float:
+    """P_2 worst-case error of the unshifted rule (z, n); exact sum in chunks."""
+    z = np.asarray(z, dtype=np.int64)
+    total = 0.0
+    two_pi2 = 2.0 * math.pi ** 2
+    for lo in range(0, n, chunk):
+        i = np.arange(lo, min(n, lo + chunk), dtype=np.int64)
+        prod = np.ones(i.shape, dtype=np.float64)
+        for zj in z:
+            x = (i * int(zj) % n).astype(np.float64) / n
+            prod *= 1.0 + two_pi2 * (x * x - x + 1.0 / 6.0)
+        total += float(np.sum(prod))
+    return total / n - 1.0
+
+
+def korobov_candidates(n: int, count: int, seed: int = 0) -> list[int]:
+    """Seeded candidate multipliers in [2, n-2] (odd when n is even)."""
+    out = []
+    for w in splitmix64(seed ^ n, 4 * count):
+        a = 2 + w % (n - 3)
+        if n % 2 == 0:
+            a |= 1
+        if math.gcd(a, n) == 1 and a not in out:
+            out.append(a)
+        if len(out) == count:
+            break
+    return out
+
+
+def search_korobov(n: int, count: int = 64, seed: int = 0) -> tuple[int, float]:
+    best = None
+    for a in korobov_candidates(n, count, seed):
+        crit = p2_criterion(n, korobov_vector(n, a, SEARCH_DIM))
+        if best is None or crit < best[1]:
+            best = (a, crit)
+    return best
+
+
+@lru_cache(maxsize=1)
+def _table() -> dict:
+    if not os.path.exists(_DATA):
+        raise FileNotFoundError(
+            f"{_DATA} is missing; run `python -m seeded_inputs.lattice`")
+    with open(_DATA) as fh:
+        return json.load(fh)
+
+
+def lattice(n: int) -> np.ndarray:
+    """Stored generating vector z[DMAX] (uint32) for lattice size n."""
+    rec = _table().get(str(n))
+    if rec is None:
+        raise KeyError(f"no stored generating vector for n={n}")
+    z = np.array(rec["z"], dtype=np.uint32)
+    assert z.shape == (DMAX,)
+    return z
+
+
+def stored_sizes() -> list[int]:
+    return sorted(int(k) for k in _table())
+
+
+def _candidate_count(n: int) -> int:
+    if n <= 1 << 20:
+        return 64
+    if n <= 1 << 24:
+        return 16
+    return 8
+
+
+def _make_one(n: int) -> tuple[int, dict]:
+    a, crit = search_korobov(n, _candidate_count(n))
+    return n, {"a": a, "p2": crit, "z": korobov_vector(n, a, DMAX),
+               "candidates": _candidate_count(n), "search_dim": SEARCH_DIM}
+
+
+def main() -> None:
+    from multiprocessing import Pool
+    sizes = sorted(set(PRIME_SIZES + POW2_SIZES), reverse=True)
+    for n in PRIME_SIZES:
+        assert is_prime(n), n
+    old = {}
+    if os.path.exists(_DATA):
+        with open(_DATA) as fh:
+            old = json.load(fh)
+    todo = [n for n in sizes if str(n) not in old]
+    with Pool(min(8, os.cpu_count() or 1)) as pool:
+        for n, rec in pool.imap_unordered(_make_one, todo):
+            old[str(n)] = rec
+            print(n, rec["a"], rec["p2"], flush=True)
+            with open(_DATA, "w") as fh:
+                json.dump({k: old[k] for k in sorted(old, key=int)}, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,74 @@
+"""Seeded inputs: RNG test vectors, lattice vectors, shifts (CPU only)."""
+
+import math
+
+import numpy as np
+
+from seeded_inputs import lattice as L
+from seeded_inputs.rng import shift_table, splitmix64
+
+
+def test_splitmix64_published_vectors():
+    # first outputs for seed 0 and 1234567 from the generator's reference
+    # implementation (Vigna, splitmix64.c)
+    assert splitmix64(0, 1)[0] == 0xE220A8397B1DCDAF
+    assert splitmix64(1234567, 3) == [6457827717110365317, 3203168211198807973,
+                                      9817491932198370423]
+
+
+def test_shift_table_shape_and_range():
+    s = shift_table(0, 10, 8)
+    assert s.shape == (10, 8)
+    assert np.all(s >= 0) and np.all(s < 1)
+    # k-major then j: the first row is the first 8 draws
+    assert np.array_equal(shift_table(0, 1, 8)[0], s[0])
+
+
+def test_p2_closed_form_one_dim():
+    # d = 1, z = 1: (1/n) sum_i B2(i/n) = 1/(6 n^2), so P2 = pi^2 / (3 n^2)
+    for n in (7, 101, 1009):
+        assert math.isclose(L.p2_criterion(n, [1]), math.pi ** 2 / (3 * n * n),
+                            rel_tol=1e-9)
+
+
+def test_p2_brute_force_two_dims():
+    n, z = 31, [1, 12]
+    direct = -1.0
+    acc = 0.0
+    for i in range(n):
+        p = 1.0
+        for zj in z:
+            x = (i * zj % n) / n
+            p *= 1 + 2 * math.pi ** 2 * (x * x - x + 1 / 6)
+        acc += p
+    direct += acc / n
+    assert math.isclose(L.p2_criterion(n, z), direct, rel_tol=1e-12)
+
+
+def test_stored_vectors_are_korobov_and_coprime():
+    for n in L.stored_sizes():
+        z = [int(v) for v in L.lattice(n)]
+        a = z[1]
+        assert z[0] == 1
+        for j in range(1, L.DMAX):
+            assert z[j] == pow(a, j, n)
+            assert math.gcd(z[j], n) == 1
+        if n in L.PRIME_SIZES:
+            assert L.is_prime(n)
+
+
+def test_dual_lattice_exactness():
+    # (1/n) sum_i exp(2 pi i h.x_i) = 1 if h.z = 0 mod n else 0   (Eq. 17)
+    n = 1009
+    z = L.lattice(n)[:3].astype(np.int64)
+    i = np.arange(n)
+    x = (np.outer(i, z) % n) / n
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        h = rng.integers(-40, 41, size=3)
+        val = np.mean(np.exp(2j * np.pi * (x @ h)))
+        expect = 1.0 if int(h @ z) % n == 0 else 0.0
+        assert abs(val - expect) < 1e-9
+    # a dual vector: h = (a, -1, 0) since a*1 - 1*a = 0
+    h = np.array([int(z[1]), -1, 0])
+    assert abs(np.mean(np.exp(2j * np.pi * (x @ h))) - 1) < 1e-9

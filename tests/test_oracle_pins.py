@@ -1,0 +1,287 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Closed forms (the one-loop bubble and box, exactly in eps or through eps^0),
+their analytic continuation to the physical region, the independence of
+the contour-deformation parameter, invariants of the periodiser and
+brute-force quadrature of individual sectors.  CPU only.
+"""
+
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import qmc
+from oracle.decompose import decompose
+from oracle.feynman import symanzik
+from seeded_inputs.lattice import lattice
+from seeded_inputs.problems import PROBLEMS
+from seeded_inputs.rng import shift_table
+
+mp.mp.dps = 30
+
+
+def _run(name, kin, n, m=8, lam=0.0, eps_hi=0, r=2):
+    return qmc.integrate(PROBLEMS[name], kin, n, lattice(n), shift_table(0, m, 8),
+                         r=r, lam=lam, eps_hi=eps_hi)
+
+
+def _check(res, exact, sigmas=6.0, floor=1e-13):
+    """|mean - exact| within `sigmas` standard errors (plus a rounding floor)."""
+    for p, want in exact.items():
+        i = res["orders"].index(p)
+        got = res["mean"][i]
+        tol_re = sigmas * res["err_re"][i] + floor * max(1.0, abs(want))
+        tol_im = sigmas * res["err_im"][i] + floor * max(1.0, abs(want))
+        assert abs(got.real - complex(want).real) <= tol_re, (p, got, want)
+        assert abs(got.imag - complex(want).imag) <= tol_im, (p, got, want)
+
+
+# --- Eq. 2: U and F ----------------------------------------------------------
+
+def test_symanzik_one_loop_textbook():
+    U, F, _ = symanzik(PROBLEMS["bubble"])
+    assert U == {(1, 0): {"1": 1}, (0, 1): {"1": 1}}
+    assert F == {(1, 1): {"s": -1}}
+    U, F, _ = symanzik(PROBLEMS["bubble_massive"])
+    # F = -s x1 x2 + m^2 (x1 + x2)^2
+    assert F == {(2, 0): {"msq": 1}, (1, 1): {"s": -1, "msq": 2},
+                 (0, 2): {"msq": 1}}
+    U, F, _ = symanzik(PROBLEMS["box"])
+    assert set(U) == {(1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1)}
+    # F = -s x1 x3 - t x2 x4
+    assert F == {(1, 0, 1, 0): {"s": -1}, (0, 1, 0, 1): {"t": -1}}
+
+
+def test_symanzik_double_box_u_from_graph():
+    # planar double box: left loop lines {1,2,3}, right loop {4,6,7}, rung 5:
+    # U = (x1+x2+x3)(x4+x6+x7) + (x1+x2+x3+x4+x6+x7) x5
+    U, F, _ = symanzik(PROBLEMS["doublebox"])
+    want = {}
+    A, B = [0, 1, 2], [3, 5, 6]
+    for i in A:
+        for j in B:
+            e = [0] * 7
+            e[i] += 1
+            e[j] += 1
+            want[tuple(e)] = {"1": 1}
+    for i in A + B:
+        e = [0] * 7
+        e[i] += 1
+        e[4] += 1
+        want[tuple(e)] = {"1": 1}
+    assert U == want
+    # F of the massless on-shell box: every term carries -s or -t only
+    for e, form in F.items():
+        assert sum(e) == 3
+        assert set(form) <= {"s", "t"}
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_symanzik_homogeneity(name):
+    prob = PROBLEMS[name]
+    U, F, _ = symanzik(prob)
+    assert all(sum(e) == prob.loops for e in U)
+    assert all(sum(e) == prob.loops + 1 for e in F)
+
+
+# --- Eqs. 3-9: decomposition ---------------------------------------------------
+
+def test_box_sector_count_and_form():
+    secs, info = decompose(PROBLEMS["box"])
+    # one primary sector of the massless box splits into 3 -> 12 in total
+    assert len(secs) == 12
+    for s in secs:
+        d = len(s["a"])
+        assert (0,) * d in s["U"] and (0,) * d in s["F"]
+        for a, b in zip(s["a"], s["b"]):
+            assert a >= 0 or (a == -1 and b != 0)
+
+
+@pytest.mark.parametrize("name", ["doublebox", "np_vertex", "triangle2l",
+                                  "doublebox_off14", "doublebox_off24",
+                                  "doublebox_off34"])
+def test_two_loop_sectors_are_regulated(name):
+    secs, _ = decompose(PROBLEMS[name])
+    for s in secs:
+        d = len(s["a"])
+        assert (0,) * d in s["U"] and (0,) * d in s["F"]
+        for a, b in zip(s["a"], s["b"]):
+            assert a >= 0 or (a == -1 and b != 0)
+
+
+def test_finite_triangle_sector_sum_equals_simplex_integral():
+    """Sum over sectors of the eps^0 integrand equals the direct Feynman
+    parameter integral over the simplex (decomposition is exact)."""
+    prob = PROBLEMS["triangle_offshell"]
+    kin = {"p1sq": -1.0, "p2sq": -2.0, "p3sq": -3.5}
+    U, F, _ = symanzik(prob)
+
+    def poly(P, x):
+        return sum(qmc.form_value(f, kin) * np.prod([xi ** ei for xi, ei in zip(x, e)], axis=0)
+                   for e, f in P.items())
+
+    # tensor Gauss-Legendre after t = psi_3(u), which smooths the integrable
+    # endpoint singularities of both integrands
+    xg, wg = np.polynomial.legendre.leggauss(48)
+    u = 0.5 * (xg + 1)
+    L = qmc.lib()
+    t = np.array([L.oracle_psi(float(v), 3) for v in u])
+    wt = np.array([L.oracle_omega(float(v), 3) for v in u]) * 0.5 * wg
+    A, B = np.meshgrid(t, t, indexing="ij")
+    W = np.outer(wt, wt)
+    # U^{-1} F^{-1} on the simplex: (x1,x2,x3) = (a, (1-a) b, (1-a)(1-b)), Jacobian 1-a
+    x = [A, (1 - A) * B, (1 - A) * (1 - B)]
+    direct = np.sum(W * (1 - A) / (poly(U, x) * poly(F, x)))
+    secs, info = decompose(prob)
+    total = 0.0
+    for s in secs:
+        ns = qmc.NumericSector(s, info, kin)
+        for i in range(len(t)):
+            for j in range(len(t)):
+                total += W[i, j] * qmc.point_value(ns, [t[i], t[j]])[0].real
+    assert abs(total - direct) < 1e-7 * abs(direct), (total, direct)
+
+
+# --- periodiser (Eq. 21 and its order-r generalisation) -------------------------
+
+@pytest.mark.parametrize("r", [0, 1, 2, 3])
+def test_periodiser_weight_integrates_to_one(r):
+    x, w = np.polynomial.legendre.leggauss(20)
+    y = 0.5 * (x + 1)
+    L = qmc.lib()
+    tot = sum(0.5 * wi * L.oracle_omega(float(yi), r) for yi, wi in zip(y, w))
+    assert abs(tot - 1.0) < 1e-13
+    for yi in (0.1, 0.37, 0.5, 0.9):
+        assert abs(L.oracle_psi(yi, r) + L.oracle_psi(1 - yi, r) - 1) < 1e-14
+
+
+def test_periodiser_r1_is_eq21_and_r2_is_korobov():
+    L = qmc.lib()
+    for y in (0.0, 0.2, 0.5, 0.77, 1.0):
+        assert abs(L.oracle_psi(y, 1) - (3 * y * y - 2 * y ** 3)) < 1e-15
+        assert abs(L.oracle_omega(y, 1) - 6 * y * (1 - y)) < 1e-15
+        assert abs(L.oracle_psi(y, 2) - (10 * y ** 3 - 15 * y ** 4 + 6 * y ** 5)) < 1e-15
+        assert abs(L.oracle_omega(y, 2) - 30 * y * y * (1 - y) ** 2) < 1e-15
+
+
+# --- closed forms -------------------------------------------------------------
+
+def _bubble_exact(s, order_hi):
+    """Gamma(eps) Gamma(1-eps)^2/Gamma(2-2eps) (-s-i0)^-eps, Laurent coeffs."""
+    L = mp.log(-s) if s < 0 else mp.log(s) - 1j * mp.pi
+    f = lambda e: mp.gamma(1 + e) * mp.gamma(1 - e) ** 2 / mp.gamma(2 - 2 * e) * mp.exp(-e * L)
+    c = mp.taylor(f, 0, order_hi + 1)
+    return {p: complex(c[p + 1]) for p in range(-1, order_hi + 1)}
+
+
+def _box_exact(s, t):
+    """r_Gamma/(s t) {2/eps^2 [(-s)^-eps + (-t)^-eps] - ln^2(s/t) - pi^2} + O(eps)."""
+    def Lm(x):
+        return mp.log(-x) if x < 0 else mp.log(x) - 1j * mp.pi
+    Ls, Lt = Lm(mp.mpf(s)), Lm(mp.mpf(t))
+    f = lambda e: (mp.gamma(1 + e) * mp.gamma(1 - e) ** 2 / mp.gamma(1 - 2 * e) / (s * t)
+                   * (2 * (mp.exp(-e * Ls) + mp.exp(-e * Lt))
+                      - e ** 2 * ((Ls - Lt) ** 2 + mp.pi ** 2)))
+    c = mp.taylor(f, 0, 2)
+    return {-2: complex(c[0]), -1: complex(c[1]), 0: complex(c[2])}
+
+
+def _massive_bubble_eps0(s, m2=1.0):
+    """eps^0 of the equal-mass bubble (eps^-1 = 1), Gamma(eps) normalisation."""
+    g = float(mp.euler)
+    if s > 4 * m2:
+        beta = math.sqrt(1 - 4 * m2 / s)
+        return complex(-g + 2 - math.log(m2) + beta * math.log((1 - beta) / (1 + beta)),
+                       math.pi * beta)
+    if s < 0:
+        beta = math.sqrt(1 - 4 * m2 / s)
+        return complex(-g + 2 - math.log(m2) + beta * math.log((beta - 1) / (beta + 1)))
+    raise ValueError
+
+
+def test_bubble_values_in_survey_table():
+    ex = _bubble_exact(-3.0, 1)
+    assert abs(ex[0] - 0.324172046430357) < 1e-14
+    assert abs(ex[1] - 1.23007672441931) < 1e-13
+    ex = _bubble_exact(3.0, 1)
+    assert abs(ex[0] - (0.324172046430357 + 3.14159265359j)) < 1e-11
+
+
+def test_oracle_massless_bubble_euclidean():
+    _check(_run("bubble", {"s": -3.0}, 10007, eps_hi=1), _bubble_exact(-3.0, 1))
+
+
+def test_oracle_massless_bubble_physical_branch():
+    # constant F = -s < 0 under the -i0 rule: (-s - i0)^-eps = s^-eps e^{i pi eps}
+    _check(_run("bubble", {"s": 3.0}, 10007, lam=0.5, eps_hi=1), _bubble_exact(3.0, 1))
+
+
+def test_oracle_massive_bubble_euclidean():
+    res = _run("bubble_massive", {"s": -3.0, "msq": 1.0}, 10007)
+    _check(res, {-1: 1.0, 0: _massive_bubble_eps0(-3.0)})
+    assert abs(res["mean"][1].real - (-0.970541032309908)) < 1e-10
+
+
+@pytest.mark.parametrize("lam", [0.1, 0.25, 0.5])
+def test_oracle_massive_bubble_above_threshold(lam):
+    res = _run("bubble_massive", {"s": 4.5, "msq": 1.0}, 10007, lam=lam)
+    want = _massive_bubble_eps0(4.5)
+    assert abs(want - (1.19173527491182 + 1.04719755119660j)) < 1e-12
+    _check(res, {-1: 1.0, 0: want}, floor=1e-9)
+    assert res["counts"][0] == 0        # Im F(z) <= 0 at every point
+
+
+def test_oracle_box_euclidean():
+    res = _run("box", {"s": -3.0, "t": -2.0}, 10007)
+    ex = _box_exact(-3.0, -2.0)
+    assert abs(ex[-1] - (-0.982063599677040)) < 1e-13
+    assert abs(ex[0] - (-1.48360889993076)) < 1e-13
+    _check(res, ex)
+
+
+def test_oracle_box_physical():
+    res = _run("box", {"s": 3.0, "t": -2.0}, 10007, lam=0.3)
+    _check(res, _box_exact(3.0, -2.0), sigmas=8.0)
+    assert res["counts"][0] == 0
+
+
+def test_oracle_converges_with_n():
+    """Shift-averaged error falls as n grows (Section III, O(1/n) rate)."""
+    ex = _box_exact(-3.0, -2.0)
+    errs = []
+    for n in (1009, 10007, 100003):
+        res = _run("box", {"s": -3.0, "t": -2.0}, n, m=4)
+        errs.append(abs(res["mean"][2] - ex[0]))
+    assert errs[1] < errs[0] / 8 and errs[2] < errs[1] / 8
+
+
+# --- the lattice machinery against brute-force quadrature per sector -----------
+
+def test_box_sectors_against_gauss_legendre():
+    """Each sector/order of the box: lattice estimate vs tensor Gauss-Legendre
+    on the untransformed cube after a smoothing substitution t = psi_3(u)."""
+    prob = PROBLEMS["box"]
+    kin = {"s": -3.0, "t": -2.0}
+    secs, info = decompose(prob)
+    xg, wg = np.polynomial.legendre.leggauss(24)
+    u = 0.5 * (xg + 1)
+    wu = 0.5 * wg
+    L = qmc.lib()
+    t = np.array([L.oracle_psi(float(v), 3) for v in u])
+    wt = np.array([L.oracle_omega(float(v), 3) for v in u]) * wu
+    n = 100003
+    z = lattice(n)
+    sh = shift_table(0, 4, 8)
+    for s in secs[:6]:
+        ns = qmc.NumericSector(s, info, kin)
+        quad = np.zeros(3, dtype=complex)
+        for i in range(24):
+            for j in range(24):
+                for k in range(24):
+                    quad += wt[i] * wt[j] * wt[k] * qmc.point_value(
+                        ns, [t[i], t[j], t[k]], out_lo=-2, out_len=3)
+        sums, _, _ = qmc.sector_sums(ns, n, z, sh, 2, 0.0, -2, 3)
+        est = sums.mean(axis=0) / n
+        assert np.all(np.abs(est - quad) < 1e-7 * (1 + np.abs(quad))), (est, quad)
