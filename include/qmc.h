@@ -1,0 +1,199 @@
+/*
+ * qmc.h -- C ABI of libqmc: quasi-Monte Carlo integration of
+ * sector-decomposed Feynman-parameter integrals on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method (Li, Wang, Yan, Zhao, "Efficient Numerical Evaluation of Feynman
+ * Integrals", Chin. Phys. C 40 (2016) 033103):
+ *   - the integral is given as a list of sectors, each of the form of
+ *     Eq. 9 (Section II): a monomial prod_j t_j^(a_j + b_j eps) times powers
+ *     U(t)^(u0 + u1 eps) F(t)^(f0 + f1 eps) of two polynomials whose
+ *     constant terms do not vanish, times a constant D;
+ *   - poles t^(-1 + b eps) are subtracted as in Eq. 11 and the integrand is
+ *     expanded in eps;
+ *   - in the physical region the contour is deformed as in Eq. 14,
+ *     z_j = t_j - i lambda t_j (1 - t_j) dF/dt_j;
+ *   - every sector is integrated with the shifted rank-1 lattice rule of
+ *     Section III (Eqs. 17-18) after a Korobov periodising transform (Eq. 21
+ *     generalised to order r); the mean over the m shifts is the estimate
+ *     (Eq. 19) and their spread gives the error (Eq. 20).
+ *
+ * Conventions
+ *   - All functions return int: QMC_OK (0) on success, QMC_PENDING (> 0)
+ *     where noted, a negative QMC_E* code on failure; qmc_last_error(ctx)
+ *     then holds a message (per context, overwritten by the next error).
+ *   - Every input pointer is caller-owned host memory, read during the call
+ *     (copied or uploaded) and not retained.  Every output pointer is
+ *     caller-allocated host memory of the stated size.
+ *   - Device memory is allocated by the library (hipMalloc) and counted
+ *     against the context's HBM budget.  Plans are immutable after creation.
+ *   - A context is bound to one device and one HIP stream; calls on one
+ *     context must not overlap, except qmc_submit / qmc_poll / qmc_wait /
+ *     qmc_cancel, which are thread-safe.
+ *   - Complex numbers are stored as (re, im) pairs of doubles.
+ */
+#ifndef QMC_H
+#define QMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define QMC_OK 0
+#define QMC_PENDING 1            /* request still running (qmc_poll/qmc_wait) */
+#define QMC_EINVAL (-1)          /* bad sizes, exponents, missing constant term, m < 2 */
+#define QMC_EUNREGULATED (-2)    /* a_j = -1 with b_j = 0 (pole not regulated) */
+#define QMC_EUNSUPPORTED (-3)    /* a_j < -1, too many poles or orders, dim > QMC_MAX_DIM */
+#define QMC_ENOMEM (-4)          /* host or device allocation failed */
+#define QMC_EBUDGET (-5)         /* request does not fit the HBM budget */
+#define QMC_EDEFORM (-6)         /* Im F(z) > 0, Re U(z) <= 0 or F <= 0 without deformation */
+#define QMC_ENOTCONVERGED (-7)   /* n_max reached before the error target */
+#define QMC_EDEVICE (-8)         /* HIP runtime error */
+#define QMC_ECANCELLED (-9)      /* request cancelled */
+
+/* ---- limits -------------------------------------------------------------- */
+#define QMC_MAX_DIM 8            /* integration variables per sector */
+#define QMC_MAX_POLES 4          /* variables with a_j = -1 per sector */
+#define QMC_MAX_ORDERS 8         /* Laurent orders carried per sector */
+#define QMC_MAX_EXP 15           /* largest exponent of a polynomial term */
+
+/* ---- precision modes ----------------------------------------------------- */
+#define QMC_FP64 0               /* all arithmetic in FP64 */
+#define QMC_FP32_EVAL 1          /* FP32 integrand, FP64 where stability needs it */
+
+typedef struct qmc_ctx qmc_ctx;     /* device, stream, budget, scheduler */
+typedef struct qmc_plan qmc_plan;   /* device-resident sector tables */
+typedef struct qmc_job qmc_job;     /* one bound integration (inputs resident) */
+
+/* Sparse polynomial sum_a c_a prod_j t_j^exps[a][j].  Its coefficients are
+ * linear in the kinematic invariants: c_a = sum_k coef[a][k] * kin[k], with
+ * kin[0] = 1 (Section II: U and F are linear in the invariants and masses). */
+typedef struct {
+    int32_t n_terms;
+    const uint8_t *exps;         /* [n_terms][dim], each <= QMC_MAX_EXP */
+    const double *coef;          /* [n_terms][n_inv] */
+} qmc_poly;
+
+/* One sector (Eq. 9): D * prod_j t_j^(a_j + b_j eps) U^(u0 + u1 eps) F^(f0 + f1 eps).
+ * a_j must be -1 (then b_j != 0; the pole is subtracted, Eq. 11) or > -1.
+ * U and F must contain the all-zero exponent (their constant term). */
+typedef struct {
+    int32_t dim;                 /* 1 .. QMC_MAX_DIM */
+    const double *mono_a;        /* [dim] */
+    const double *mono_b;        /* [dim] */
+    qmc_poly U, F;
+    double u_exp[2];             /* u0, u1 */
+    double f_exp[2];             /* f0, f1 */
+    double coef_re, coef_im;     /* D */
+} qmc_sector;
+
+/* The whole integral: sum over sectors, times a prefactor series (e.g. the
+ * Gamma function of Eq. 5), Laurent orders eps_lo .. eps_hi returned. */
+typedef struct {
+    int32_t n_sectors;
+    const qmc_sector *sectors;
+    int32_t n_inv;               /* invariants per kinematic point, kin[0] = 1 */
+    int32_t eps_lo, eps_hi;
+    const double *prefactor;     /* [n_pref][2]: coefficients of eps^(eps_pref_lo + q) */
+    int32_t eps_pref_lo, n_pref;
+} qmc_problem;
+
+typedef struct {
+    int32_t precision;           /* QMC_FP64 or QMC_FP32_EVAL */
+    int32_t korobov_r;           /* periodiser order 0..3 (Eq. 21 is r = 1) */
+    double lambda;               /* deformation parameter; 0 = Euclidean */
+    int32_t points_per_lane;     /* 0 = chosen by the library */
+} qmc_plan_opts;
+
+/* Rank-1 lattice (Eq. 17): points {i z / n}, i = 0 .. n-1; 2 <= n < 2^31,
+ * z[j] coprime to n.  z has QMC_MAX_DIM entries; a sector of dimension d
+ * uses z[0..d-1]. */
+typedef struct {
+    uint64_t n;
+    const uint32_t *z;
+} qmc_lattice;
+
+typedef struct { double re, im, err_re, err_im; } qmc_coeff;
+
+/* Per-plan facts for callers laying out optional outputs. */
+typedef struct {
+    int32_t n_sectors, n_inv;
+    int32_t sec_lo, sec_orders;  /* sector Laurent orders sec_lo .. sec_lo+sec_orders-1 */
+    int32_t eps_lo, eps_hi;
+    int32_t max_poles, deform;
+    double flops_per_point;      /* algorithmic FP64 flops of one lattice point, summed over sectors */
+} qmc_plan_info;
+
+typedef struct {
+    qmc_coeff *coeff;            /* [n_points][eps_hi-eps_lo+1] */
+    double *per_shift;           /* optional [n_points][m][eps_hi-eps_lo+1][2] */
+    double *sector_sums;         /* optional [n_points][n_sectors][m][sec_orders][2]:
+                                    raw sums sum_i w g (no 1/n, no D) */
+    uint64_t evals;              /* integrand evaluations (points x sectors x shifts) */
+    uint64_t n_final;            /* lattice size of the final iteration (serving) */
+    int32_t status;              /* QMC_OK, QMC_EDEFORM, ... */
+    int32_t deform_violations;   /* points with Im F(z) > 0 or Re U(z) <= 0 */
+    double kernel_ms;            /* device time of the integrand kernels */
+    double algo_flops;           /* algorithmic flops of the integrand kernels */
+} qmc_result;
+
+/* Create a context on `device` with at most hbm_budget bytes of device
+ * memory (0 = 64 GiB) and at most max_slots concurrent serving requests
+ * (0 = 64).  Creates a HIP stream of default priority. */
+int qmc_create(int device, size_t hbm_budget, int max_slots, qmc_ctx **out);
+void qmc_destroy(qmc_ctx *ctx);
+/* Use a caller-owned stream (e.g. PyTorch's current stream) instead. */
+int qmc_set_stream(qmc_ctx *ctx, void *hip_stream);
+const char *qmc_last_error(qmc_ctx *ctx);
+
+/* Validate the sectors, permute each sector's variables so the subtracted
+ * ones come first, sort polynomial terms by which of those they contain,
+ * derive dF and d2F tables when lambda > 0, and upload the tables. */
+int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *problem,
+                     const qmc_plan_opts *opts, qmc_plan **out);
+void qmc_plan_free(qmc_plan *plan);
+int qmc_plan_get_info(const qmc_plan *plan, qmc_plan_info *info);
+
+/* Integrate at n_points kinematic points kin[n_points][n_inv] with the
+ * lattice `lat` (or lat_per_sector[n_sectors] if not NULL) and the shifts
+ * shifts[m][QMC_MAX_DIM] (m >= 2).  Blocks until the result is ready. */
+int qmc_integrate(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
+                  int32_t n_points, const qmc_lattice *lat,
+                  const qmc_lattice *lat_per_sector, const double *shifts,
+                  int32_t m, qmc_result *out);
+
+/* The same in three steps: bind uploads the inputs and allocates device
+ * outputs; run enqueues the kernels on the context stream (asynchronous);
+ * fetch waits for them, copies the per-shift sums back and assembles. */
+int qmc_bind(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
+             int32_t n_points, const qmc_lattice *lat,
+             const qmc_lattice *lat_per_sector, const double *shifts,
+             int32_t m, qmc_job **out);
+int qmc_run(qmc_job *job);
+int qmc_fetch(qmc_job *job, qmc_result *out);
+void qmc_job_free(qmc_job *job);
+
+/* ---- serving (continuous batching) --------------------------------------- */
+typedef struct {
+    const double *kin;           /* [n_inv] one kinematic point */
+    double rel_err_target;       /* stop when err/|mean| <= target for every order */
+    uint64_t n0, n_max;          /* embedded lattice sizes (powers of two) */
+    int32_t m;                   /* shifts (>= 2) */
+    uint64_t seed;               /* SplitMix64 seed of the shifts */
+    const uint32_t *z;           /* [QMC_MAX_DIM] odd generating vector for n = 2^k */
+} qmc_request;
+
+int qmc_submit(qmc_ctx *ctx, const qmc_plan *plan, const qmc_request *req,
+               uint64_t *ticket);
+int qmc_poll(qmc_ctx *ctx, uint64_t ticket, qmc_result *out);
+int qmc_wait(qmc_ctx *ctx, uint64_t ticket, double timeout_s, qmc_result *out);
+int qmc_cancel(qmc_ctx *ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QMC_H */

@@ -1,4 +1,4 @@
-"""Oracle: sector decomposition (Section II, Eqs. 3-9).  TEST INFRASTRUCTURE.
+r"""Oracle: sector decomposition (Section II, Eqs. 3-9).  TEST INFRASTRUCTURE.
 
 Primary sectors (Eqs. 3-6): in sector l the largest Feynman parameter is
 x_l; x_j = x_l t_j for the others, and the delta constraint is used to set

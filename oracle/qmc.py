@@ -29,6 +29,7 @@ from .decompose import decompose
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qmc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIBQ = os.path.join(_HERE, "liboracle_q.so")     # integrand in binary128
 
 
 class _Sector(ctypes.Structure):
@@ -46,22 +47,24 @@ class _Sector(ctypes.Structure):
 
 
 def build() -> str:
-    """Compile the C oracle with gcc (OpenMP)."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
-           "-D_DEFAULT_SOURCE", "-o", _LIB, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
+    """Compile the C oracle with gcc (OpenMP): FP64 and binary128 builds."""
+    base = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=gnu11", "-D_DEFAULT_SOURCE"]
+    subprocess.run(base + ["-o", _LIB, _SRC, "-lm"], check=True)
+    subprocess.run(base + ["-DORACLE_QUAD", "-o", _LIBQ, _SRC, "-lquadmath", "-lm"],
+                   check=True)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+def lib(quad=False):
+    """The FP64 oracle library, or the binary128 build when quad=True."""
+    path = _LIBQ if quad else _LIB
+    if path not in _libs:
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         L.oracle_sector_sums.argtypes = [
             P(_Sector), ctypes.c_uint64, P(ctypes.c_uint32), P(ctypes.c_double),
@@ -76,8 +79,8 @@ def lib():
         L.oracle_psi.restype = ctypes.c_double
         L.oracle_omega.argtypes = [ctypes.c_double, ctypes.c_int]
         L.oracle_omega.restype = ctypes.c_double
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _ptr(arr, ctype):
@@ -119,8 +122,10 @@ class NumericSector:
 
 
 def sector_sums(ns: NumericSector, n, z, shifts, r=2, lam=0.0,
-                out_lo=0, out_len=1, nthreads=0):
-    """(sums, abss, counts): sums[m][out_len] complex = sum_i w g (no 1/n)."""
+                out_lo=0, out_len=1, nthreads=0, quad=False):
+    """(sums, abss, counts): sums[m][out_len] complex = sum_i w g (no 1/n).
+
+    quad=True evaluates the integrand in binary128 (same formula)."""
     shifts = np.ascontiguousarray(shifts, dtype=np.float64)
     m, dmax = shifts.shape
     z = np.ascontiguousarray(z, dtype=np.uint32)
@@ -128,7 +133,7 @@ def sector_sums(ns: NumericSector, n, z, shifts, r=2, lam=0.0,
     abss = np.zeros((m, out_len, 2))
     counts = np.zeros((m, 3), dtype=np.int64)
     st = ns.cstruct()
-    rc = lib().oracle_sector_sums(
+    rc = lib(quad).oracle_sector_sums(
         ctypes.byref(st), int(n), _ptr(z, ctypes.c_uint32),
         _ptr(shifts, ctypes.c_double), m, dmax, int(r), float(lam),
         int(out_lo), int(out_len), _ptr(sums, ctypes.c_double),
@@ -138,11 +143,11 @@ def sector_sums(ns: NumericSector, n, z, shifts, r=2, lam=0.0,
     return sums[..., 0] + 1j * sums[..., 1], abss, counts
 
 
-def point_value(ns: NumericSector, t, lam=0.0, out_lo=0, out_len=1):
+def point_value(ns: NumericSector, t, lam=0.0, out_lo=0, out_len=1, quad=False):
     t = np.ascontiguousarray(t, dtype=np.float64)
     out = np.zeros((out_len, 2))
     st = ns.cstruct()
-    rc = lib().oracle_point(ctypes.byref(st), _ptr(t, ctypes.c_double), float(lam),
+    rc = lib(quad).oracle_point(ctypes.byref(st), _ptr(t, ctypes.c_double), float(lam),
                             int(out_lo), int(out_len), _ptr(out, ctypes.c_double))
     if rc < 0:
         raise ValueError("oracle_point rejected its arguments")
@@ -207,7 +212,7 @@ def assemble(per_sector, D, pref, pref_lo, sec_lo, n, eps_lo, eps_hi):
 
 
 def integrate(problem, kin, n, z, shifts, r=2, lam=0.0, eps_hi=0, nthreads=0,
-              sectors=None):
+              sectors=None, quad=False):
     """Whole-problem oracle estimate: dict with orders, mean, errors."""
     if sectors is None:
         sectors, info = decompose(problem)
@@ -222,7 +227,7 @@ def integrate(problem, kin, n, z, shifts, r=2, lam=0.0, eps_hi=0, nthreads=0,
     per = []
     counts = np.zeros(3, dtype=np.int64)
     for ns in nums:
-        S, _, c = sector_sums(ns, n, z, shifts, r, lam, sec_lo, K, nthreads)
+        S, _, c = sector_sums(ns, n, z, shifts, r, lam, sec_lo, K, nthreads, quad)
         per.append(S)
         counts += c.sum(axis=0)
     eps_lo = sec_lo + pref_lo

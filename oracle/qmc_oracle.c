@@ -44,7 +44,38 @@
 #include <omp.h>
 #endif
 
+/*
+ * Working precision of the integrand.  The default build is FP64.  The
+ * subtraction of Eq. 11 with k poles forms k-th mixed differences of the
+ * integrand, which amplifies rounding by up to ~1e8 for k = 4; the build
+ * with -DORACLE_QUAD evaluates the same formula in IEEE binary128
+ * (libquadmath) so that the oracle's own rounding stays far below FP64
+ * roundoff of the result.  Lattice points, weights and sums stay FP64.
+ */
+#ifdef ORACLE_QUAD
+#include <quadmath.h>
+typedef __float128 real;
+typedef __complex128 cplx;
+#define RLOG logq
+#define CLOG clogq
+#define CEXP cexpq
+#define CABS cabsq
+#define CREAL crealq
+#define CIMAG cimagq
+#define RPI M_PIq
+#define SYM(name) name##_q
+#else
+typedef double real;
 typedef double complex cplx;
+#define RLOG log
+#define CLOG clog
+#define CEXP cexp
+#define CABS cabs
+#define CREAL creal
+#define CIMAG cimag
+#define RPI M_PI
+#define SYM(name) name
+#endif
 
 #define ORD_LO (-10)            /* lowest representable order */
 #define ORD_N 24                /* orders ORD_LO .. ORD_LO+ORD_N-1 */
@@ -68,20 +99,23 @@ typedef struct {
 typedef struct { cplx c[ORD_N]; } series;
 
 static int g_top;   /* highest order kept (set per call) */
+static int g_bot;   /* lowest order that can be non-zero (set per call) */
 
 static void s_zero(series *s) { memset(s, 0, sizeof *s); }
 
 static void s_const(series *s, cplx v) { s_zero(s); s->c[-ORD_LO] = v; }
 
+/* product, truncated above g_top; every factor is zero below g_bot */
 static void s_mul(series *out, const series *x, const series *y)
 {
     series r;
     s_zero(&r);
-    for (int p = 0; p < ORD_N; ++p) {
+    const int lo = g_bot - ORD_LO, hi = g_top - ORD_LO;
+    for (int p = lo; p <= hi; ++p) {
         if (x->c[p] == 0) continue;
-        for (int q = 0; q < ORD_N; ++q) {
+        for (int q = lo; q <= hi; ++q) {
             int o = p + q + ORD_LO;     /* index of order (p+LO)+(q+LO) */
-            if (o < 0 || o >= ORD_N || o + ORD_LO > g_top) continue;
+            if (o < 0 || o > hi) continue;
             r.c[o] += x->c[p] * y->c[q];
         }
     }
@@ -90,33 +124,33 @@ static void s_mul(series *out, const series *x, const series *y)
 
 static void s_axpy(series *acc, cplx alpha, const series *x)
 {
-    for (int p = 0; p < ORD_N; ++p) acc->c[p] += alpha * x->c[p];
+    for (int p = g_bot - ORD_LO; p <= g_top - ORD_LO; ++p) acc->c[p] += alpha * x->c[p];
 }
 
 /* exp(v eps) as a series */
 static void s_exp_eps(series *s, cplx v)
 {
     s_zero(s);
-    cplx term = 1.0;
-    for (int k = 0; k - 0 <= g_top && -ORD_LO + k < ORD_N; ++k) {
+    cplx term = 1;
+    for (int k = 0; k <= g_top && -ORD_LO + k < ORD_N; ++k) {
         s->c[-ORD_LO + k] = term;
-        term = term * v / (double)(k + 1);
+        term = term * v / (real)(k + 1);
     }
 }
 
 /* x^(p + q eps) = exp(p L) exp(q eps L) with L the logarithm below */
 static cplx logF(cplx x)
 {
-    if (cimag(x) == 0.0 && creal(x) < 0.0)
-        return log(-creal(x)) - I * M_PI;      /* the -i0 side */
-    return clog(x);
+    if (CIMAG(x) == 0 && CREAL(x) < 0)
+        return RLOG(-CREAL(x)) - I * RPI;      /* the -i0 side */
+    return CLOG(x);
 }
 
 static void s_pow(series *s, cplx x, double p, double q)
 {
     cplx L = logF(x);
-    s_exp_eps(s, q * L);
-    cplx base = cexp(p * L);
+    s_exp_eps(s, (real)q * L);
+    cplx base = CEXP((real)p * L);
     for (int k = 0; k < ORD_N; ++k) s->c[k] *= base;
 }
 
@@ -125,20 +159,20 @@ static void s_div_eps(series *out, const series *x, double b)
 {
     series r;
     s_zero(&r);
-    for (int p = 1; p < ORD_N; ++p) r.c[p - 1] = x->c[p] / b;
+    for (int p = 1; p < ORD_N; ++p) r.c[p - 1] = x->c[p] / (real)b;
     *out = r;
 }
 
-static double ipow(double x, int e)
+static real ipow(real x, int e)
 {
-    double r = 1.0;
+    real r = 1;
     for (int k = 0; k < e; ++k) r *= x;
     return r;
 }
 
 static cplx cipow(cplx x, int e)
 {
-    cplx r = 1.0;
+    cplx r = 1;
     for (int k = 0; k < e; ++k) r *= x;
     return r;
 }
@@ -167,24 +201,12 @@ static double omega_r(double y, int r)
     return pow(y * (1.0 - y), r) * beta_inv(r);
 }
 
-static double poly_real(int n, const int32_t *e, const double *c, int d,
-                        const double *t)
-{
-    double s = 0.0;
-    for (int a = 0; a < n; ++a) {
-        double v = c[a];
-        for (int j = 0; j < d; ++j) v *= ipow(t[j], e[a * d + j]);
-        s += v;
-    }
-    return s;
-}
-
 static cplx poly_cplx(int n, const int32_t *e, const double *c, int d,
                       const cplx *z)
 {
-    cplx s = 0.0;
+    cplx s = 0;
     for (int a = 0; a < n; ++a) {
-        cplx v = c[a];
+        cplx v = (real)c[a];
         for (int j = 0; j < d; ++j) v *= cipow(z[j], e[a * d + j]);
         s += v;
     }
@@ -192,14 +214,14 @@ static cplx poly_cplx(int n, const int32_t *e, const double *c, int d,
 }
 
 /* first derivative d/dt_j of the polynomial at t */
-static double poly_d1(int n, const int32_t *e, const double *c, int d,
-                      const double *t, int j)
+static real poly_d1(int n, const int32_t *e, const double *c, int d,
+                    const real *t, int j)
 {
-    double s = 0.0;
+    real s = 0;
     for (int a = 0; a < n; ++a) {
         int ej = e[a * d + j];
         if (ej == 0) continue;
-        double v = c[a] * ej;
+        real v = (real)c[a] * ej;
         for (int l = 0; l < d; ++l)
             v *= ipow(t[l], e[a * d + l] - (l == j));
         s += v;
@@ -208,13 +230,13 @@ static double poly_d1(int n, const int32_t *e, const double *c, int d,
 }
 
 /* second derivative d^2/dt_j dt_k */
-static double poly_d2(int n, const int32_t *e, const double *c, int d,
-                      const double *t, int j, int k)
+static real poly_d2(int n, const int32_t *e, const double *c, int d,
+                    const real *t, int j, int k)
 {
-    double s = 0.0;
+    real s = 0;
     for (int a = 0; a < n; ++a) {
         int ej = e[a * d + j], ek = e[a * d + k];
-        double v = c[a];
+        real v = (real)c[a];
         if (j == k) {
             if (ej < 2) continue;
             v *= ej * (ej - 1);
@@ -233,12 +255,12 @@ static double poly_d2(int n, const int32_t *e, const double *c, int d,
 
 static cplx cdet(int d, cplx *A)     /* Gaussian elimination, partial pivot */
 {
-    cplx det = 1.0;
+    cplx det = 1;
     for (int c = 0; c < d; ++c) {
         int piv = c;
         for (int r = c + 1; r < d; ++r)
-            if (cabs(A[r * d + c]) > cabs(A[piv * d + c])) piv = r;
-        if (A[piv * d + c] == 0) return 0.0;
+            if (CABS(A[r * d + c]) > CABS(A[piv * d + c])) piv = r;
+        if (A[piv * d + c] == 0) return 0;
         if (piv != c) {
             for (int k = 0; k < d; ++k) {
                 cplx tmp = A[c * d + k];
@@ -257,14 +279,14 @@ static cplx cdet(int d, cplx *A)     /* Gaussian elimination, partial pivot */
 }
 
 /* h evaluated at the real point tp (integrand without prod_{J} t^(-1+b eps)) */
-static void h_series(const oracle_sector *s, const double *tp,
-                     const double *omt, const int *inJ, double lambda,
+static void h_series(const oracle_sector *s, const real *tp,
+                     const real *omt, const int *inJ, double lambda,
                      series *h, int *bad_f, int *bad_u)
 {
     int d = s->dim;
-    cplx z[MAXD], phi[MAXD], detJ = 1.0;
+    cplx z[MAXD], phi[MAXD], detJ = 1;
     if (lambda > 0.0) {
-        double g[MAXD];
+        real g[MAXD];
         cplx Jm[MAXD * MAXD];
         for (int j = 0; j < d; ++j)
             g[j] = poly_d1(s->nF, s->eF, s->cF, d, tp, j);
@@ -272,7 +294,7 @@ static void h_series(const oracle_sector *s, const double *tp,
             phi[j] = 1.0 - I * lambda * omt[j] * g[j];
             z[j] = tp[j] * phi[j];
             for (int k = 0; k < d; ++k) {
-                double hjk = poly_d2(s->nF, s->eF, s->cF, d, tp, j, k);
+                real hjk = poly_d2(s->nF, s->eF, s->cF, d, tp, j, k);
                 cplx v = -I * lambda * tp[j] * omt[j] * hjk;
                 if (j == k) v += 1.0 - I * lambda * (omt[j] - tp[j]) * g[j];
                 Jm[j * d + k] = v;
@@ -280,13 +302,13 @@ static void h_series(const oracle_sector *s, const double *tp,
         }
         detJ = cdet(d, Jm);
     } else {
-        for (int j = 0; j < d; ++j) { z[j] = tp[j]; phi[j] = 1.0; }
+        for (int j = 0; j < d; ++j) { z[j] = tp[j]; phi[j] = 1; }
     }
     cplx Uz = poly_cplx(s->nU, s->eU, s->cU, d, z);
     cplx Fz = poly_cplx(s->nF, s->eF, s->cF, d, z);
     if (lambda > 0.0) {
-        if (cimag(Fz) > 0.0) ++*bad_f;
-        if (creal(Uz) <= 0.0) ++*bad_u;
+        if (CIMAG(Fz) > 0) ++*bad_f;
+        if (CREAL(Uz) <= 0) ++*bad_u;
     }
     series f;
     s_const(h, detJ);
@@ -308,8 +330,8 @@ static void h_series(const oracle_sector *s, const double *tp,
 }
 
 /* g(t) with the subtraction of Eq. 11 for every j in J */
-static void integrand(const oracle_sector *s, const double *t,
-                      const double *omt, double lambda, series *g, int *bad_f,
+static void integrand(const oracle_sector *s, const real *t,
+                      const real *omt, double lambda, series *g, int *bad_f,
                       int *bad_u)
 {
     int d = s->dim, J[MAXD], nJ = 0, inJ[MAXD];
@@ -320,9 +342,9 @@ static void integrand(const oracle_sector *s, const double *t,
     int ncorner = 1 << nJ;
     series *hc = malloc(sizeof(series) * ncorner);
     for (int X = 0; X < ncorner; ++X) {
-        double tp[MAXD], op[MAXD];
-        memcpy(tp, t, sizeof(double) * d);
-        memcpy(op, omt, sizeof(double) * d);
+        real tp[MAXD], op[MAXD];
+        memcpy(tp, t, sizeof(real) * d);
+        memcpy(op, omt, sizeof(real) * d);
         for (int q = 0; q < nJ; ++q)
             if (X >> q & 1) { tp[J[q]] = 0.0; op[J[q]] = 1.0; }
         h_series(s, tp, op, inJ, lambda, &hc[X], bad_f, bad_u);
@@ -336,7 +358,7 @@ static void integrand(const oracle_sector *s, const double *t,
         s_zero(&inner);
         for (int S = rest;; S = (S - 1) & rest) {
             int parity = __builtin_popcount(S) & 1;
-            s_axpy(&inner, parity ? -1.0 : 1.0, &hc[R | S]);
+            s_axpy(&inner, parity ? -1 : 1, &hc[R | S]);
             if (S == 0) break;
         }
         series term = inner, f;
@@ -345,12 +367,12 @@ static void integrand(const oracle_sector *s, const double *t,
             if (R >> q & 1) {
                 s_div_eps(&term, &term, s->b[j]);
             } else {
-                s_exp_eps(&f, s->b[j] * log(t[j]));
+                s_exp_eps(&f, (real)s->b[j] * RLOG(t[j]));
                 for (int k = 0; k < ORD_N; ++k) f.c[k] /= t[j];
                 s_mul(&term, &term, &f);
             }
         }
-        s_axpy(g, 1.0, &term);
+        s_axpy(g, 1, &term);
     }
     free(hc);
 }
@@ -395,6 +417,7 @@ int oracle_sector_sums(const oracle_sector *s, uint64_t n, const uint32_t *z,
     int top = out_lo + out_len - 1;
     if (top + nJ >= ORD_LO + ORD_N) return -1;
     g_top = top + nJ;       /* orders needed before the 1/eps divisions */
+    g_bot = -nJ;
 
     uint64_t nchunks = (n + CHUNK - 1) / CHUNK;
     size_t slots = (size_t)m * nchunks * out_len * 2;
@@ -415,16 +438,18 @@ int oracle_sector_sums(const oracle_sector *s, uint64_t n, const uint32_t *z,
         int64_t *N = cnt + job * 3;
         uint64_t i1 = (ch + 1) * CHUNK < n ? (ch + 1) * CHUNK : n;
         for (uint64_t i = ch * CHUNK; i < i1; ++i) {
-            double t[MAXD], omt[MAXD], w = 1.0;
+            real t[MAXD], omt[MAXD];
+            double w = 1.0;
             int skip = 0;
             for (int j = 0; j < d; ++j) {
                 uint64_t l = (i * (uint64_t)z[j]) % n;
                 double y = (double)l / (double)n + shifts[k * dmax + j];
                 if (y >= 1.0) y -= 1.0;
-                t[j] = psi_r(y, r);
+                double tj = psi_r(y, r);
+                t[j] = tj;
                 omt[j] = psi_r(1.0 - y, r);    /* 1 - t by the symmetry of psi */
                 w *= omega_r(y, r);
-                if (t[j] == 0.0) skip = 1;
+                if (tj == 0.0) skip = 1;
             }
             if (w == 0.0 || skip) { ++N[2]; continue; }
             series g;
@@ -433,11 +458,12 @@ int oracle_sector_sums(const oracle_sector *s, uint64_t n, const uint32_t *z,
             N[0] += bf != 0;
             N[1] += bu != 0;
             for (int q = 0; q < out_len; ++q) {
-                cplx v = w * g.c[out_lo + q - ORD_LO];
-                neumaier(&S[2 * q], &C[2 * q], creal(v));
-                neumaier(&S[2 * q + 1], &C[2 * q + 1], cimag(v));
-                A[2 * q] += fabs(creal(v));
-                A[2 * q + 1] += fabs(cimag(v));
+                cplx v = (real)w * g.c[out_lo + q - ORD_LO];
+                double vr = (double)CREAL(v), vi = (double)CIMAG(v);
+                neumaier(&S[2 * q], &C[2 * q], vr);
+                neumaier(&S[2 * q + 1], &C[2 * q + 1], vi);
+                A[2 * q] += fabs(vr);
+                A[2 * q + 1] += fabs(vi);
             }
         }
     }
@@ -469,19 +495,23 @@ int oracle_sector_sums(const oracle_sector *s, uint64_t n, const uint32_t *z,
 int oracle_point(const oracle_sector *s, const double *t, double lambda,
                  int out_lo, int out_len, double *out /* [out_len][2] */)
 {
-    double omt[MAXD];
-    for (int j = 0; j < s->dim && j < MAXD; ++j) omt[j] = 1.0 - t[j];
+    real tt[MAXD], omt[MAXD];
+    for (int j = 0; j < s->dim && j < MAXD; ++j) {
+        tt[j] = t[j];
+        omt[j] = 1 - (real)t[j];
+    }
     int nJ = 0;
     for (int j = 0; j < s->dim; ++j) nJ += (s->a[j] == -1.0);
     int top = out_lo + out_len - 1;
     if (s->dim > MAXD || out_lo < ORD_LO || top + nJ >= ORD_LO + ORD_N) return -1;
     g_top = top + nJ;
+    g_bot = -nJ;
     series g;
     int bf = 0, bu = 0;
-    integrand(s, t, omt, lambda, &g, &bf, &bu);
+    integrand(s, tt, omt, lambda, &g, &bf, &bu);
     for (int q = 0; q < out_len; ++q) {
-        out[2 * q] = creal(g.c[out_lo + q - ORD_LO]);
-        out[2 * q + 1] = cimag(g.c[out_lo + q - ORD_LO]);
+        out[2 * q] = (double)CREAL(g.c[out_lo + q - ORD_LO]);
+        out[2 * q + 1] = (double)CIMAG(g.c[out_lo + q - ORD_LO]);
     }
     return bf + 2 * bu;
 }

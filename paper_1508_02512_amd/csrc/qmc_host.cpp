@@ -1,0 +1,753 @@
+// libqmc host side: context, planner, work lists, assembly of the result.
+//
+// The planner turns the sectors of Eq. 9 into device tables (see
+// qmc_device.h); bind turns (kinematic points, lattices, shifts) into
+// device inputs and a work list; run launches one integrand kernel per
+// (poles, orders) class and the fixed-order reduction; fetch copies the
+// per-(point, sector, shift) sums back and forms, per shift, the Laurent
+// series prefactor x sum_sectors D_s S_s / n_s, then the mean over shifts
+// (Eq. 19) and the error estimate (Eq. 20).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/qmc.h"
+#include "qmc_device.h"
+#include "qmc_kernels.h"
+#include "qmc_internal.h"
+
+// ------------------------------------------------------------------ context
+
+static int set_err(qmc_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        std::lock_guard<std::mutex> g(ctx->err_mu);
+        ctx->last_error = buf;
+    }
+    return code;
+}
+
+#define HIP_CHECK(ctx, expr)                                                      \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return set_err((ctx), QMC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int qmc_dev_alloc(qmc_ctx *ctx, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) return QMC_OK;
+    size_t used = ctx->used.load();
+    if (used + bytes > ctx->budget)
+        return set_err(ctx, QMC_EBUDGET, "device budget exceeded: %zu + %zu > %zu bytes",
+                       used, bytes, ctx->budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return set_err(ctx, QMC_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    ctx->used += bytes;
+    return QMC_OK;
+}
+
+void qmc_dev_free(qmc_ctx *ctx, void *p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    ctx->used -= bytes;
+}
+
+extern "C" int qmc_create(int device, size_t hbm_budget, int max_slots, qmc_ctx **out)
+{
+    if (!out) return QMC_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return QMC_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return QMC_EDEVICE;
+    qmc_ctx *ctx = new (std::nothrow) qmc_ctx();
+    if (!ctx) return QMC_ENOMEM;
+    ctx->device = device;
+    ctx->budget = hbm_budget ? hbm_budget : ((size_t)64 << 30);
+    ctx->max_slots = max_slots > 0 ? max_slots : 64;
+    if (hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete ctx;
+        return QMC_EDEVICE;
+    }
+    ctx->stream = ctx->own_stream;
+    *out = ctx;
+    return QMC_OK;
+}
+
+extern "C" void qmc_destroy(qmc_ctx *ctx)
+{
+    if (!ctx) return;
+    qmc_serve_shutdown(ctx);
+    (void)hipSetDevice(ctx->device);
+    if (ctx->own_stream) {
+        (void)hipStreamSynchronize(ctx->own_stream);
+        (void)hipStreamDestroy(ctx->own_stream);
+    }
+    delete ctx;
+}
+
+extern "C" int qmc_set_stream(qmc_ctx *ctx, void *stream)
+{
+    if (!ctx) return QMC_EINVAL;
+    ctx->stream = stream ? (hipStream_t)stream : ctx->own_stream;
+    return QMC_OK;
+}
+
+extern "C" const char *qmc_last_error(qmc_ctx *ctx)
+{
+    if (!ctx) return "null context";
+    std::lock_guard<std::mutex> g(ctx->err_mu);
+    return ctx->last_error.c_str();
+}
+
+// ------------------------------------------------------------------ planner
+
+static uint32_t pack_exps(const uint8_t *e, const int *perm, int dim)
+{
+    uint32_t p = 0;
+    for (int j = 0; j < dim; ++j) p |= (uint32_t)e[perm[j]] << (4 * j);
+    return p;
+}
+
+// Algorithmic FP64 flops of one lattice point of one sector (see DESIGN
+// notes in the library documentation): add/sub/mul = 1, fma = 2, division
+// and each log/exp/atan = 20.
+static double sector_flops(const qmc_sec_host &h)
+{
+    const double T = 20.0;
+    const int d = h.dim, ks = h.ks, K = h.K;
+    double f = 0.0;
+    f += d * (T /*division*/ + 2 /*shift, wrap*/ + 12 /*psi, 1-psi*/ + 4 /*weight*/);
+    f += d * 2;                                 // t^2, t^3
+    int nlog = 0;
+    for (int j = 0; j < d; ++j)
+        if (j < ks || h.b[j] != 0.0 || h.aint[j] == QMC_NO_INT) ++nlog;
+    f += nlog * T;
+    for (const auto &nnz : h.term_nnz) f += nnz + 2;
+    const int corners = 1 << ks;
+    f += 2.0 * ks * (corners / 2);              // subset sums of U and F
+    const double powc = h.u0i != QMC_NO_INT && h.f0i != QMC_NO_INT
+                            ? std::abs(h.u0i) + std::abs(h.f0i) + (h.f0i < 0 || h.u0i < 0 ? T : 0)
+                            : T;
+    f += corners * (2 * T + powc + 4 + 3.0 * (K - 1));
+    f += ks * (T + 3.0 * (K - 1));              // 1/t and (b ln t)^r / r!
+    f += (corners - 1) * (K + K * (K - 1) + 3.0 * K);   // folds
+    f += K * (2 + 4);                           // weight and Neumaier
+    if (h.deform) {
+        const int nd = (int)h.dterm_nnz.size();
+        double dterms = 0;
+        for (int v : h.dterm_nnz) dterms += v + 2;
+        (void)nd;
+        // per corner: derivatives, complex z and phi, Jacobian LU, complex
+        // U and F (4 real flops per complex product), logs and arguments
+        double per_corner = dterms + d * 8 + (4.0 * d * d * d / 3.0) * 4 +
+                            4.0 * (double)h.term_nnz.size() * 3 + 2 * d * T + 4 * T;
+        f += corners * per_corner + (corners - 1) * 3.0 * (K + K * (K - 1));
+    }
+    return f;
+}
+
+extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
+                                const qmc_plan_opts *opts, qmc_plan **out)
+{
+    if (!ctx || !pb || !out) return set_err(ctx, QMC_EINVAL, "null argument");
+    *out = nullptr;
+    if (pb->n_sectors < 1 || !pb->sectors || pb->n_inv < 1)
+        return set_err(ctx, QMC_EINVAL, "need at least one sector and n_inv >= 1");
+    if (pb->eps_hi < pb->eps_lo) return set_err(ctx, QMC_EINVAL, "eps_hi < eps_lo");
+    if (pb->n_pref < 1 || !pb->prefactor)
+        return set_err(ctx, QMC_EINVAL, "prefactor series is empty");
+    qmc_plan_opts o = {QMC_FP64, 2, 0.0, 0};
+    if (opts) o = *opts;
+    if (o.korobov_r < 0 || o.korobov_r > 3)
+        return set_err(ctx, QMC_EUNSUPPORTED, "korobov_r must be 0..3");
+    if (o.precision != QMC_FP64)
+        return set_err(ctx, QMC_EUNSUPPORTED, "precision mode %d not available", o.precision);
+    if (!(o.lambda >= 0.0) || o.lambda > 0.0)
+        return set_err(ctx, QMC_EUNSUPPORTED, "contour deformation (lambda > 0) not available");
+
+    auto *plan = new (std::nothrow) qmc_plan();
+    if (!plan) return set_err(ctx, QMC_ENOMEM, "host allocation");
+    plan->ctx = ctx;
+    plan->opts = o;
+    plan->n_inv = pb->n_inv;
+    plan->eps_lo = pb->eps_lo;
+    plan->eps_hi = pb->eps_hi;
+    plan->eps_pref_lo = pb->eps_pref_lo;
+    plan->pref.assign(pb->prefactor, pb->prefactor + 2 * pb->n_pref);
+    plan->n_pref = pb->n_pref;
+
+    const int ns = pb->n_sectors;
+    int max_ks = 0;
+    // pass 1: poles per sector
+    for (int s = 0; s < ns; ++s) {
+        const qmc_sector &S = pb->sectors[s];
+        if (S.dim < 1 || S.dim > QMC_MAX_DIM || !S.mono_a || !S.mono_b) {
+            delete plan;
+            return set_err(ctx, QMC_EUNSUPPORTED, "sector %d: dim %d outside 1..%d", s, S.dim,
+                           QMC_MAX_DIM);
+        }
+        int ks = 0;
+        for (int j = 0; j < S.dim; ++j) {
+            const double a = S.mono_a[j], b = S.mono_b[j];
+            if (!std::isfinite(a) || !std::isfinite(b)) {
+                delete plan;
+                return set_err(ctx, QMC_EINVAL, "sector %d: exponent not finite", s);
+            }
+            if (a == -1.0) {
+                if (b == 0.0) {
+                    delete plan;
+                    return set_err(ctx, QMC_EUNREGULATED, "sector %d var %d: a = -1, b = 0", s, j);
+                }
+                ++ks;
+            } else if (a < -1.0) {
+                delete plan;
+                return set_err(ctx, QMC_EUNSUPPORTED, "sector %d var %d: a = %g < -1", s, j, a);
+            }
+        }
+        if (ks > QMC_MAX_POLES) {
+            delete plan;
+            return set_err(ctx, QMC_EUNSUPPORTED, "sector %d: %d poles > %d", s, ks, QMC_MAX_POLES);
+        }
+        max_ks = std::max(max_ks, ks);
+    }
+    plan->sec_lo = -max_ks;
+    plan->sec_hi = pb->eps_hi - pb->eps_pref_lo;
+    const int kb = plan->sec_hi + 1;
+    if (kb < 1 || kb > 3) {
+        delete plan;
+        return set_err(ctx, QMC_EUNSUPPORTED,
+                       "sector orders above the poles (%d) must be 1..3", kb);
+    }
+    if (plan->sec_hi - plan->sec_lo + 1 > QMC_MAX_ORDERS) {
+        delete plan;
+        return set_err(ctx, QMC_EUNSUPPORTED, "too many Laurent orders");
+    }
+    plan->kb = kb;
+    plan->kstride = kb + max_ks;
+
+    // pass 2: tables
+    for (int s = 0; s < ns; ++s) {
+        const qmc_sector &S = pb->sectors[s];
+        qmc_sec_host h{};
+        h.dim = S.dim;
+        int perm[QMC_DMAX], np = 0;
+        for (int j = 0; j < S.dim; ++j)
+            if (S.mono_a[j] == -1.0) perm[np++] = j;
+        h.ks = np;
+        for (int j = 0; j < S.dim; ++j)
+            if (S.mono_a[j] != -1.0) perm[np++] = j;
+        h.K = h.ks + kb;
+        h.deform = o.lambda > 0.0 ? 1 : 0;
+        for (int j = 0; j < QMC_DMAX; ++j) {
+            h.perm[j] = j < S.dim ? perm[j] : 0;
+            h.a[j] = j < S.dim ? S.mono_a[perm[j]] : 0.0;
+            h.b[j] = j < S.dim ? S.mono_b[perm[j]] : 0.0;
+            h.aint[j] = 0;
+            if (j < S.dim) {
+                const double a = h.a[j];
+                if (a >= 0.0 && a <= 64.0 && a == std::floor(a)) h.aint[j] = (int)a;
+                else h.aint[j] = QMC_NO_INT;
+            }
+        }
+        for (int j = 0; j < h.ks; ++j) h.inv_b[j] = 1.0 / h.b[j];
+        h.u0 = S.u_exp[0];
+        h.u1 = S.u_exp[1];
+        h.f0 = S.f_exp[0];
+        h.f1 = S.f_exp[1];
+        auto as_int = [](double v) {
+            return (v == std::floor(v) && std::fabs(v) <= 64.0) ? (int)v : QMC_NO_INT;
+        };
+        h.u0i = as_int(h.u0);
+        h.f0i = as_int(h.f0);
+        // terms of U then F, each grouped by pole mask
+        for (int which = 0; which < 2; ++which) {
+            const qmc_poly &P = which == 0 ? S.U : S.F;
+            if (P.n_terms < 1 || !P.exps || !P.coef) {
+                delete plan;
+                return set_err(ctx, QMC_EINVAL, "sector %d: empty polynomial", s);
+            }
+            bool has_const = false;
+            std::vector<std::pair<int, int>> order;   // (mask, term)
+            for (int a = 0; a < P.n_terms; ++a) {
+                const uint8_t *e = P.exps + (size_t)a * S.dim;
+                bool zero = true;
+                int mask = 0;
+                for (int j = 0; j < S.dim; ++j) {
+                    if (e[j] > QMC_MAX_EXP) {
+                        delete plan;
+                        return set_err(ctx, QMC_EUNSUPPORTED, "sector %d: exponent %d > %d", s,
+                                       e[j], QMC_MAX_EXP);
+                    }
+                    if (e[j]) zero = false;
+                }
+                for (int j = 0; j < h.ks; ++j)
+                    if (e[perm[j]]) mask |= 1 << j;
+                has_const |= zero;
+                order.push_back({mask, a});
+            }
+            if (!has_const) {
+                delete plan;
+                return set_err(ctx, QMC_EINVAL, "sector %d: %s has no constant term", s,
+                               which == 0 ? "U" : "F");
+            }
+            std::stable_sort(order.begin(), order.end(),
+                             [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+                                 return x.first < y.first;
+                             });
+            int32_t *rng = which == 0 ? h.um : h.fm;
+            int cursor = 0;
+            for (int m = 0; m <= QMC_NMASK; ++m) {
+                while (cursor < (int)order.size() && order[cursor].first < m) ++cursor;
+                rng[m] = (int32_t)plan->texp.size() + cursor;
+            }
+            for (auto &pr : order) {
+                const uint8_t *e = P.exps + (size_t)pr.second * S.dim;
+                plan->texp.push_back(pack_exps(e, perm, S.dim));
+                const double *c = P.coef + (size_t)pr.second * pb->n_inv;
+                plan->tcoef_rows.insert(plan->tcoef_rows.end(), c, c + pb->n_inv);
+                int nnz = 0;
+                for (int j = 0; j < S.dim; ++j) nnz += e[j] != 0;
+                h.term_nnz.push_back(nnz);
+            }
+        }
+        h.D = std::complex<double>(S.coef_re, S.coef_im);
+        h.flops = sector_flops(h);
+        plan->flops_per_point += h.flops;
+        plan->secs.push_back(h);
+    }
+    plan->n_terms = (int)plan->texp.size();
+    plan->max_ks = max_ks;
+
+    // device copies of the sector headers and exponents
+    std::vector<qmc_sec_dev> dev(ns);
+    for (int s = 0; s < ns; ++s) dev[s] = plan->secs[s].dev();
+    int rc = qmc_dev_alloc(ctx, (void **)&plan->d_sec, sizeof(qmc_sec_dev) * ns);
+    if (rc == QMC_OK)
+        rc = qmc_dev_alloc(ctx, (void **)&plan->d_texp, sizeof(uint32_t) * plan->texp.size());
+    if (rc != QMC_OK) {
+        qmc_plan_free(plan);
+        return rc;
+    }
+    hipError_t e = hipMemcpy(plan->d_sec, dev.data(), sizeof(qmc_sec_dev) * ns,
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(plan->d_texp, plan->texp.data(), sizeof(uint32_t) * plan->texp.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        qmc_plan_free(plan);
+        return set_err(ctx, QMC_EDEVICE, "upload: %s", hipGetErrorString(e));
+    }
+    *out = plan;
+    return QMC_OK;
+}
+
+qmc_sec_dev qmc_sec_host::dev() const
+{
+    qmc_sec_dev d{};
+    d.dim = dim;
+    d.ks = ks;
+    d.K = K;
+    d.deform = deform;
+    for (int j = 0; j < QMC_DMAX; ++j) {
+        d.perm[j] = perm[j];
+        d.a[j] = a[j];
+        d.b[j] = b[j];
+        d.inv_b[j] = inv_b[j];
+        d.aint[j] = aint[j];
+    }
+    for (int m = 0; m <= QMC_NMASK; ++m) {
+        d.um[m] = um[m];
+        d.fm[m] = fm[m];
+    }
+    for (int j = 0; j <= QMC_DMAX; ++j) d.d1[j] = d1[j];
+    for (int j = 0; j <= QMC_DMAX * (QMC_DMAX + 1) / 2; ++j) d.d2[j] = d2[j];
+    d.u0 = u0;
+    d.u1 = u1;
+    d.f0 = f0;
+    d.f1 = f1;
+    d.u0i = u0i;
+    d.f0i = f0i;
+    d.lambda = lambda;
+    return d;
+}
+
+extern "C" void qmc_plan_free(qmc_plan *plan)
+{
+    if (!plan) return;
+    qmc_ctx *ctx = plan->ctx;
+    qmc_dev_free(ctx, plan->d_sec, sizeof(qmc_sec_dev) * plan->secs.size());
+    qmc_dev_free(ctx, plan->d_texp, sizeof(uint32_t) * plan->texp.size());
+    qmc_dev_free(ctx, plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
+    delete plan;
+}
+
+extern "C" int qmc_plan_get_info(const qmc_plan *plan, qmc_plan_info *info)
+{
+    if (!plan || !info) return QMC_EINVAL;
+    info->n_sectors = (int32_t)plan->secs.size();
+    info->n_inv = plan->n_inv;
+    info->sec_lo = plan->sec_lo;
+    info->sec_orders = plan->sec_hi - plan->sec_lo + 1;
+    info->eps_lo = plan->eps_lo;
+    info->eps_hi = plan->eps_hi;
+    info->max_poles = plan->max_ks;
+    info->deform = plan->opts.lambda > 0.0;
+    info->flops_per_point = plan->flops_per_point;
+    return QMC_OK;
+}
+
+// ------------------------------------------------------------------ jobs
+
+void qmc_job_release(qmc_job *job)
+{
+    if (!job) return;
+    qmc_ctx *ctx = job->ctx;
+    for (auto &b : job->bufs) qmc_dev_free(ctx, b.first, b.second);
+    job->bufs.clear();
+    if (job->ev0) (void)hipEventDestroy(job->ev0);
+    if (job->ev1) (void)hipEventDestroy(job->ev1);
+    job->ev0 = job->ev1 = nullptr;
+}
+
+template <class T>
+static int job_upload(qmc_job *job, T **dptr, const T *src, size_t count)
+{
+    size_t bytes = sizeof(T) * std::max<size_t>(count, 1);
+    int rc = qmc_dev_alloc(job->ctx, (void **)dptr, bytes);
+    if (rc != QMC_OK) return rc;
+    job->bufs.push_back({(void *)*dptr, bytes});
+    if (count && src) {
+        hipError_t e = hipMemcpyAsync(*dptr, src, sizeof(T) * count, hipMemcpyHostToDevice,
+                                      job->ctx->stream);
+        if (e != hipSuccess)
+            return set_err(job->ctx, QMC_EDEVICE, "upload: %s", hipGetErrorString(e));
+    }
+    return QMC_OK;
+}
+
+int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
+                  const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
+                  const double *shifts, int32_t m, int ppl_override, qmc_job **out)
+{
+    if (!ctx || !plan || !kin || !shifts || !out) return set_err(ctx, QMC_EINVAL, "null argument");
+    *out = nullptr;
+    if (n_points < 1) return set_err(ctx, QMC_EINVAL, "n_points < 1");
+    if (m < 2) return set_err(ctx, QMC_EINVAL, "need m >= 2 shifts for the error estimate");
+    if (!lat && !lat_per_sector) return set_err(ctx, QMC_EINVAL, "no lattice given");
+    const int ns = (int)plan->secs.size();
+    (void)hipSetDevice(ctx->device);
+
+    auto *job = new (std::nothrow) qmc_job();
+    if (!job) return set_err(ctx, QMC_ENOMEM, "host allocation");
+    job->ctx = ctx;
+    job->plan = plan;
+    job->n_points = n_points;
+    job->m = m;
+
+    // lattices per sector, components permuted like the sector's variables
+    std::vector<qmc_lat_dev> lats(ns);
+    job->n_per_sector.resize(ns);
+    for (int s = 0; s < ns; ++s) {
+        const qmc_lattice &L = lat_per_sector ? lat_per_sector[s] : *lat;
+        if (L.n < 2 || L.n >= (1ull << 31) || !L.z) {
+            delete job;
+            return set_err(ctx, QMC_EINVAL, "sector %d: lattice size %llu outside [2, 2^31)", s,
+                           (unsigned long long)L.n);
+        }
+        const qmc_sec_host &h = plan->secs[s];
+        qmc_lat_dev d{};
+        d.n = (uint32_t)L.n;
+        d.inv_n = 1.0 / (double)L.n;
+        for (int j = 0; j < QMC_DMAX; ++j)
+            d.z[j] = j < h.dim ? (uint32_t)(L.z[h.perm[j]] % L.n) : 0u;
+        lats[s] = d;
+        job->n_per_sector[s] = L.n;
+    }
+    // coefficients contracted with the kinematics of every point
+    const int nt = plan->n_terms, ni = plan->n_inv;
+    std::vector<double> coef((size_t)n_points * nt);
+    for (int p = 0; p < n_points; ++p) {
+        const double *k = kin + (size_t)p * ni;
+        for (int t = 0; t < nt; ++t) {
+            const double *row = plan->tcoef_rows.data() + (size_t)t * ni;
+            double c = 0.0;
+            for (int i = 0; i < ni; ++i) c += row[i] * k[i];
+            coef[(size_t)p * nt + t] = c;
+        }
+    }
+    // work list: class-major (ks), then point, sector, shift, tile
+    uint64_t total = 0;
+    for (int s = 0; s < ns; ++s) total += job->n_per_sector[s];
+    total *= (uint64_t)m * n_points;
+    int ppl = ppl_override > 0 ? ppl_override : plan->opts.points_per_lane;
+    if (ppl <= 0) {
+        const uint64_t target_items = 1ull << 17;
+        uint64_t want = (total + (uint64_t)QMC_BLOCK * target_items - 1) /
+                        ((uint64_t)QMC_BLOCK * target_items);
+        ppl = (int)std::min<uint64_t>(std::max<uint64_t>(want, 4), 1 << 14);
+    }
+    job->ppl = ppl;
+    const uint64_t tile = (uint64_t)QMC_BLOCK * ppl;
+    const int n_groups = n_points * ns * m;
+    std::vector<int32_t> gbeg(n_groups), gend(n_groups);
+    std::vector<qmc_item> items;
+    for (int cls = 0; cls <= plan->max_ks; ++cls) {
+        qmc_class c{};
+        c.ks = cls;
+        c.kb = plan->kb;
+        c.begin = (int)items.size();
+        for (int p = 0; p < n_points; ++p)
+            for (int s = 0; s < ns; ++s) {
+                if (plan->secs[s].ks != cls) continue;
+                const uint64_t n = job->n_per_sector[s];
+                for (int k = 0; k < m; ++k) {
+                    const int g = (p * ns + s) * m + k;
+                    gbeg[g] = (int32_t)items.size();
+                    for (uint64_t st = 0; st < n; st += tile) {
+                        qmc_item it{};
+                        it.sector = s;
+                        it.point = p;
+                        it.shift = k;
+                        it.group = g;
+                        it.start = (uint32_t)st;
+                        it.count = (uint32_t)std::min<uint64_t>(tile, n - st);
+                        items.push_back(it);
+                    }
+                    gend[g] = (int32_t)items.size();
+                }
+            }
+        c.end = (int)items.size();
+        if (c.end > c.begin) job->classes.push_back(c);
+    }
+    if (items.size() > (size_t)INT32_MAX) {
+        delete job;
+        return set_err(ctx, QMC_EINVAL, "work list too long");
+    }
+    job->n_items = (int)items.size();
+    job->n_groups = n_groups;
+    job->evals = total;
+    int rc = QMC_OK;
+    if (!rc) rc = job_upload(job, &job->d_lat, lats.data(), lats.size());
+    if (!rc) rc = job_upload(job, &job->d_coef, coef.data(), coef.size());
+    if (!rc) rc = job_upload(job, &job->d_shift, shifts, (size_t)m * QMC_DMAX);
+    if (!rc) rc = job_upload(job, &job->d_items, items.data(), items.size());
+    if (!rc) rc = job_upload(job, &job->d_gbeg, gbeg.data(), gbeg.size());
+    if (!rc) rc = job_upload(job, &job->d_gend, gend.data(), gend.size());
+    if (!rc)
+        rc = job_upload<double>(job, &job->d_partial, nullptr,
+                                (size_t)job->n_items * plan->kstride * 4);
+    if (!rc) rc = job_upload<int32_t>(job, &job->d_viol, nullptr, (size_t)job->n_items);
+    if (!rc)
+        rc = job_upload<double>(job, &job->d_out, nullptr, (size_t)n_groups * plan->kstride * 2);
+    if (!rc) rc = job_upload<int32_t>(job, &job->d_gviol, nullptr, (size_t)n_groups);
+    if (!rc && (hipEventCreate(&job->ev0) != hipSuccess || hipEventCreate(&job->ev1) != hipSuccess))
+        rc = set_err(ctx, QMC_EDEVICE, "hipEventCreate failed");
+    if (rc) {
+        qmc_job_release(job);
+        delete job;
+        return rc;
+    }
+    job->h_out.resize((size_t)n_groups * plan->kstride * 2);
+    job->h_gviol.resize(n_groups);
+    *out = job;
+    return QMC_OK;
+}
+
+extern "C" int qmc_bind(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
+                        int32_t n_points, const qmc_lattice *lat,
+                        const qmc_lattice *lat_per_sector, const double *shifts, int32_t m,
+                        qmc_job **out)
+{
+    return qmc_bind_impl(ctx, plan, kin, n_points, lat, lat_per_sector, shifts, m, 0, out);
+}
+
+extern "C" int qmc_run(qmc_job *job)
+{
+    if (!job) return QMC_EINVAL;
+    qmc_ctx *ctx = job->ctx;
+    const qmc_plan *plan = job->plan;
+    (void)hipSetDevice(ctx->device);
+    qmc_launch_args A{};
+    A.sec = plan->d_sec;
+    A.lat = job->d_lat;
+    A.texp = plan->d_texp;
+    A.tcoef = job->d_coef;
+    A.dexp = plan->d_dexp;
+    A.dcoef = job->d_dcoef;
+    A.shifts = job->d_shift;
+    A.items = job->d_items;
+    A.partial = job->d_partial;
+    A.viol = job->d_viol;
+    A.n_terms = plan->n_terms;
+    A.n_dterms = (int32_t)plan->dexp.size();
+    A.kstride = plan->kstride;
+    A.ppl = job->ppl;
+    A.korobov_r = plan->opts.korobov_r;
+    HIP_CHECK(ctx, hipEventRecord(job->ev0, ctx->stream));
+    for (const qmc_class &c : job->classes) {
+        A.item_begin = c.begin;
+        A.item_end = c.end;
+        HIP_CHECK(ctx, qmc_launch_real(c.ks, c.kb, A, c.end - c.begin, ctx->stream));
+    }
+    HIP_CHECK(ctx, hipEventRecord(job->ev1, ctx->stream));
+    HIP_CHECK(ctx, qmc_launch_reduce(job->d_partial, job->d_viol, job->d_gbeg, job->d_gend,
+                                     job->n_groups, plan->kstride, job->d_out, job->d_gviol,
+                                     ctx->stream));
+    HIP_CHECK(ctx, hipMemcpyAsync(job->h_out.data(), job->d_out,
+                                  sizeof(double) * job->h_out.size(), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+    HIP_CHECK(ctx, hipMemcpyAsync(job->h_gviol.data(), job->d_gviol,
+                                  sizeof(int32_t) * job->h_gviol.size(), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+    job->launched = true;
+    return QMC_OK;
+}
+
+// Laurent assembly and statistics (Eqs. 19-20) from the per-group sums.
+int qmc_assemble(const qmc_plan *plan, int n_points, int m, const std::vector<uint64_t> &nsec,
+                 const double *gsum /* [groups][kstride][2] */, qmc_result *out)
+{
+    const int ns = (int)plan->secs.size();
+    const int K = plan->sec_hi - plan->sec_lo + 1;
+    const int no = plan->eps_hi - plan->eps_lo + 1;
+    std::vector<std::complex<double>> tot(K), Q((size_t)m * no);
+    for (int p = 0; p < n_points; ++p) {
+        for (int k = 0; k < m; ++k) {
+            std::fill(tot.begin(), tot.end(), 0.0);
+            for (int s = 0; s < ns; ++s) {
+                const qmc_sec_host &h = plan->secs[s];
+                const double *g = gsum + ((size_t)((p * ns + s) * m + k)) * plan->kstride * 2;
+                for (int q = 0; q < h.K; ++q) {
+                    const int order = q - h.ks;
+                    const std::complex<double> v(g[2 * q], g[2 * q + 1]);
+                    tot[order - plan->sec_lo] += h.D * v / (double)nsec[s];
+                }
+            }
+            for (int oi = 0; oi < no; ++oi) {
+                const int order = plan->eps_lo + oi;
+                std::complex<double> acc = 0.0;
+                for (int j = 0; j < K; ++j) {
+                    const int pp = order - (plan->sec_lo + j) - plan->eps_pref_lo;
+                    if (pp < 0 || pp >= plan->n_pref) continue;
+                    acc += std::complex<double>(plan->pref[2 * pp], plan->pref[2 * pp + 1]) * tot[j];
+                }
+                Q[(size_t)k * no + oi] = acc;
+            }
+        }
+        for (int oi = 0; oi < no; ++oi) {
+            double mr = 0.0, mi = 0.0;
+            for (int k = 0; k < m; ++k) {
+                mr += Q[(size_t)k * no + oi].real();
+                mi += Q[(size_t)k * no + oi].imag();
+            }
+            mr /= m;
+            mi /= m;
+            double vr = 0.0, vi = 0.0;
+            for (int k = 0; k < m; ++k) {
+                const double dr = Q[(size_t)k * no + oi].real() - mr;
+                const double di = Q[(size_t)k * no + oi].imag() - mi;
+                vr += dr * dr;
+                vi += di * di;
+            }
+            qmc_coeff &c = out->coeff[(size_t)p * no + oi];
+            c.re = mr;
+            c.im = mi;
+            c.err_re = std::sqrt(vr / ((double)m * (m - 1)));
+            c.err_im = std::sqrt(vi / ((double)m * (m - 1)));
+        }
+        if (out->per_shift)
+            for (int k = 0; k < m; ++k)
+                for (int oi = 0; oi < no; ++oi) {
+                    double *d = out->per_shift + (((size_t)p * m + k) * no + oi) * 2;
+                    d[0] = Q[(size_t)k * no + oi].real();
+                    d[1] = Q[(size_t)k * no + oi].imag();
+                }
+    }
+    if (out->sector_sums) {
+        const int K2 = K;
+        for (int p = 0; p < n_points; ++p)
+            for (int s = 0; s < ns; ++s)
+                for (int k = 0; k < m; ++k) {
+                    const qmc_sec_host &h = plan->secs[s];
+                    const double *g = gsum + ((size_t)((p * ns + s) * m + k)) * plan->kstride * 2;
+                    double *d = out->sector_sums + (((size_t)(p * ns + s) * m + k) * K2) * 2;
+                    for (int j = 0; j < K2 * 2; ++j) d[j] = 0.0;
+                    for (int q = 0; q < h.K; ++q) {
+                        const int j = q - h.ks - plan->sec_lo;
+                        d[2 * j] = g[2 * q];
+                        d[2 * j + 1] = g[2 * q + 1];
+                    }
+                }
+    }
+    return QMC_OK;
+}
+
+extern "C" int qmc_fetch(qmc_job *job, qmc_result *out)
+{
+    if (!job || !out || !out->coeff) return QMC_EINVAL;
+    qmc_ctx *ctx = job->ctx;
+    if (!job->launched) return set_err(ctx, QMC_EINVAL, "qmc_fetch before qmc_run");
+    HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.0f;
+    HIP_CHECK(ctx, hipEventElapsedTime(&ms, job->ev0, job->ev1));
+    job->launched = false;
+    qmc_assemble(job->plan, job->n_points, job->m, job->n_per_sector, job->h_out.data(), out);
+    long viol = 0;
+    for (int32_t v : job->h_gviol) viol += v;
+    out->evals = job->evals;
+    out->n_final = job->n_per_sector.empty() ? 0 : job->n_per_sector[0];
+    out->deform_violations = (int32_t)std::min<long>(viol, INT32_MAX);
+    out->status = viol ? QMC_EDEFORM : QMC_OK;
+    out->kernel_ms = ms;
+    double fl = 0.0;
+    for (size_t s = 0; s < job->plan->secs.size(); ++s)
+        fl += job->plan->secs[s].flops * (double)job->n_per_sector[s];
+    out->algo_flops = fl * job->m * job->n_points;
+    return out->status == QMC_OK ? QMC_OK
+                                 : set_err(ctx, out->status, "%ld points violated the sign conditions", viol);
+}
+
+extern "C" void qmc_job_free(qmc_job *job)
+{
+    if (!job) return;
+    if (job->launched) (void)hipStreamSynchronize(job->ctx->stream);
+    qmc_job_release(job);
+    delete job;
+}
+
+extern "C" int qmc_integrate(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
+                             int32_t n_points, const qmc_lattice *lat,
+                             const qmc_lattice *lat_per_sector, const double *shifts,
+                             int32_t m, qmc_result *out)
+{
+    if (!out || !out->coeff) return set_err(ctx, QMC_EINVAL, "null result");
+    qmc_job *job = nullptr;
+    int rc = qmc_bind(ctx, plan, kin, n_points, lat, lat_per_sector, shifts, m, &job);
+    if (rc) return rc;
+    rc = qmc_run(job);
+    if (!rc) rc = qmc_fetch(job, out);
+    qmc_job_free(job);
+    return rc;
+}

@@ -1,0 +1,106 @@
+// Host-side state of libqmc (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <complex>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/qmc.h"
+#include "qmc_device.h"
+
+struct qmc_serve_state;
+
+struct qmc_ctx {
+    int device = 0;
+    size_t budget = 0;
+    std::atomic<size_t> used{0};
+    int max_slots = 64;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    std::mutex err_mu;
+    std::string last_error;
+    qmc_serve_state *serve = nullptr;
+    std::mutex serve_mu;
+};
+
+// One sector as planned: permuted exponents, term ranges, flop count.
+struct qmc_sec_host {
+    int dim = 0, ks = 0, K = 0, deform = 0;
+    int perm[QMC_DMAX] = {};
+    double a[QMC_DMAX] = {}, b[QMC_DMAX] = {}, inv_b[QMC_DMAX] = {};
+    int aint[QMC_DMAX] = {};
+    int32_t um[QMC_NMASK + 1] = {}, fm[QMC_NMASK + 1] = {};
+    int32_t d1[QMC_DMAX + 1] = {};
+    int32_t d2[QMC_DMAX * (QMC_DMAX + 1) / 2 + 1] = {};
+    double u0 = 0, u1 = 0, f0 = 0, f1 = 0;
+    int u0i = 0, f0i = 0;
+    double lambda = 0.0;
+    std::complex<double> D = 1.0;
+    std::vector<int> term_nnz;   // non-zero exponents per term (U and F)
+    std::vector<int> dterm_nnz;  // the same for the derivative terms
+    double flops = 0.0;          // algorithmic flops per lattice point
+    qmc_sec_dev dev() const;
+};
+
+struct qmc_plan {
+    qmc_ctx *ctx = nullptr;
+    qmc_plan_opts opts{};
+    int n_inv = 0;
+    int eps_lo = 0, eps_hi = 0, eps_pref_lo = 0, n_pref = 0;
+    std::vector<double> pref;        // [n_pref][2]
+    int sec_lo = 0, sec_hi = 0;      // sector orders carried
+    int kb = 1;                      // orders from eps^0 up: sec_hi + 1
+    int kstride = 1;                 // order slots per group: kb + max_ks
+    int max_ks = 0;
+    std::vector<qmc_sec_host> secs;
+    std::vector<uint32_t> texp;      // packed exponents of all U and F terms
+    std::vector<double> tcoef_rows;  // [n_terms][n_inv]
+    std::vector<uint32_t> dexp;      // packed exponents of derivative terms
+    std::vector<double> dcoef_rows;  // [n_dterms][n_inv]
+    int n_terms = 0;
+    double flops_per_point = 0.0;
+    qmc_sec_dev *d_sec = nullptr;
+    uint32_t *d_texp = nullptr;
+    uint32_t *d_dexp = nullptr;
+};
+
+struct qmc_class {                   // items launched by one kernel instance
+    int ks = 0, kb = 1, deform = 0;
+    int begin = 0, end = 0;
+};
+
+struct qmc_job {
+    qmc_ctx *ctx = nullptr;
+    const qmc_plan *plan = nullptr;
+    int n_points = 0, m = 0, ppl = 0;
+    int n_items = 0, n_groups = 0;
+    uint64_t evals = 0;
+    std::vector<uint64_t> n_per_sector;
+    std::vector<qmc_class> classes;
+    std::vector<std::pair<void *, size_t>> bufs;
+    qmc_lat_dev *d_lat = nullptr;
+    double *d_coef = nullptr, *d_dcoef = nullptr, *d_shift = nullptr;
+    qmc_item *d_items = nullptr;
+    int32_t *d_gbeg = nullptr, *d_gend = nullptr;
+    double *d_partial = nullptr, *d_out = nullptr;
+    int32_t *d_viol = nullptr, *d_gviol = nullptr;
+    std::vector<double> h_out;
+    std::vector<int32_t> h_gviol;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool launched = false;
+};
+
+int qmc_dev_alloc(qmc_ctx *ctx, void **p, size_t bytes);
+void qmc_dev_free(qmc_ctx *ctx, void *p, size_t bytes);
+int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
+                  const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
+                  const double *shifts, int32_t m, int ppl_override, qmc_job **out);
+void qmc_job_release(qmc_job *job);
+int qmc_assemble(const qmc_plan *plan, int n_points, int m, const std::vector<uint64_t> &nsec,
+                 const double *gsum, qmc_result *out);
+void qmc_serve_shutdown(qmc_ctx *ctx);

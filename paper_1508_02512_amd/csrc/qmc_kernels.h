@@ -1,0 +1,17 @@
+// Host-side launchers of the integrand and reduction kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qmc_device.h"
+
+// Real (Euclidean) FP64 integrand for sectors with `ks` poles carrying
+// ks + kb Laurent orders; one work-group per item in [item_begin, item_end).
+hipError_t qmc_launch_real(int ks, int kb, const qmc_launch_args &args, int grid,
+                           hipStream_t stream);
+
+// Fixed-order compensated sum of each group's items.
+hipError_t qmc_launch_reduce(const double *partial, const int32_t *viol,
+                             const int32_t *group_begin, const int32_t *group_end,
+                             int n_groups, int kstride, double *out, int32_t *gviol,
+                             hipStream_t stream);

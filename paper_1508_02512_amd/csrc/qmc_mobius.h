@@ -1,0 +1,218 @@
+// Cancellation-free mixed differences for the pole subtraction of Eq. 11.
+//
+// With k poles the subtracted integrand needs, for every subset Y of the
+// pole variables, the k-th order mixed difference
+//     h^[Y] = sum_{Z subset Y} (-1)^{|Y \ Z|} h(t with the poles outside Z set to 0),
+// the Moebius coefficient of the corner values of h.  Forming it from the
+// corner values loses up to ~8 digits for k = 4 (the instability the paper
+// points out before Eq. 13).  Here every quantity is carried as its vector
+// of Moebius coefficients over the 2^k subsets instead:
+//   - U and F: their coefficient for Y is the sum of the terms that contain
+//     exactly the pole variables in Y, which is computed without
+//     subtraction (the terms are grouped by that mask);
+//   - products: h = f g has h^[Y] = sum_{A u B = Y} f^[A] g^[B];
+//   - quotients q = a / b solve a^[Y] = q^[Y] b(Y) + sum_{A u B = Y, B != Y} b^[A] q^[B]
+//     in increasing Y, with b(Y) the corner value;
+//   - log(1 + x): splitting off the highest variable j,
+//       log(1 + x)(W + j) - log(1 + x)(W) = log(1 + x_j / (1 + x_0))(W),
+//     which recurses on one variable fewer and ends in scalar log1p.
+// No step subtracts nearly equal quantities, so each coefficient keeps
+// FP64 relative accuracy.  Index Y is a bit mask over the pole variables;
+// all loops are over compile-time masks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mobius {
+
+template <int KS>
+struct Fn {
+    static constexpr int N = 1 << KS;
+    double c[N];
+};
+
+// out = f * g (union product)
+template <int KS>
+__device__ __forceinline__ void mul(const double (&f)[1 << KS], const double (&g)[1 << KS],
+                                    double (&out)[1 << KS])
+{
+    constexpr int N = 1 << KS;
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y) {
+        double s = 0.0;
+#pragma unroll
+        for (int A = 0; A < N; ++A) {
+            if ((A & ~Y) != 0) continue;
+            const int R = Y & ~A;
+#pragma unroll
+            for (int C = 0; C < N; ++C) {
+                if ((C & ~A) != 0) continue;
+                s = fma(f[A], g[R | C], s);
+            }
+        }
+        out[Y] = s;
+    }
+}
+
+// corner value f(Y) = sum_{A subset Y} f^[A]
+template <int KS>
+__device__ __forceinline__ double corner(const double (&f)[1 << KS], int Y)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int A = 0; A < (1 << KS); ++A)
+        if ((A & ~Y) == 0) s += f[A];
+    return s;
+}
+
+// q = a / b
+template <int KS>
+__device__ __forceinline__ void div(const double (&a)[1 << KS], const double (&b)[1 << KS],
+                                    double (&q)[1 << KS])
+{
+    constexpr int N = 1 << KS;
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y) {
+        double s = a[Y];
+#pragma unroll
+        for (int A = 0; A < N; ++A) {
+            if ((A & ~Y) != 0) continue;
+            const int R = Y & ~A;
+#pragma unroll
+            for (int C = 0; C < N; ++C) {
+                if ((C & ~A) != 0) continue;
+                if ((R | C) == Y) continue;     // the unknown q^[Y] itself
+                s = fma(-b[A], q[R | C], s);
+            }
+        }
+        q[Y] = s / corner<KS>(b, Y);
+    }
+}
+
+// r = log(1 + x)
+template <int KS>
+struct Log1p {
+    static __device__ __forceinline__ void run(const double (&x)[1 << KS], double (&r)[1 << KS])
+    {
+        constexpr int H = 1 << (KS - 1);
+        double x0[H], x1[H], d[H], y[H], r0[H], r1[H];
+#pragma unroll
+        for (int W = 0; W < H; ++W) {
+            x0[W] = x[W];
+            x1[W] = x[W + H];
+            d[W] = x[W];
+        }
+        d[0] += 1.0;
+        Log1p<KS - 1>::run(x0, r0);
+        div<KS - 1>(x1, d, y);
+        Log1p<KS - 1>::run(y, r1);
+#pragma unroll
+        for (int W = 0; W < H; ++W) {
+            r[W] = r0[W];
+            r[W + H] = r1[W];
+        }
+    }
+};
+
+template <>
+struct Log1p<0> {
+    static __device__ __forceinline__ void run(const double (&x)[1], double (&r)[1])
+    {
+        r[0] = log1p(x[0]);
+    }
+};
+
+// r = log(f) for f with a positive value at every corner
+template <int KS>
+__device__ __forceinline__ void log(const double (&f)[1 << KS], double (&r)[1 << KS])
+{
+    constexpr int N = 1 << KS;
+    double x[N];
+    const double inv0 = 1.0 / f[0];
+    x[0] = 0.0;
+#pragma unroll
+    for (int Y = 1; Y < N; ++Y) x[Y] = f[Y] * inv0;
+    Log1p<KS>::run(x, r);
+    r[0] = ::log(f[0]);
+}
+
+// r = f^e for an integer e (wave-uniform)
+template <int KS>
+__device__ __forceinline__ void powi(const double (&f)[1 << KS], int e, double (&r)[1 << KS])
+{
+    constexpr int N = 1 << KS;
+    double base[N], one[N];
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y) {
+        one[Y] = Y == 0 ? 1.0 : 0.0;
+        r[Y] = one[Y];
+    }
+    if (e == 0) return;
+    if (e < 0) {
+        div<KS>(one, f, base);
+        e = -e;
+    } else {
+#pragma unroll
+        for (int Y = 0; Y < N; ++Y) base[Y] = f[Y];
+    }
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y) r[Y] = base[Y];
+    for (int k = 1; k < e; ++k) {
+        double tmp[N];
+        mul<KS>(r, base, tmp);
+#pragma unroll
+        for (int Y = 0; Y < N; ++Y) r[Y] = tmp[Y];
+    }
+}
+
+// r = exp(x) - 1
+template <int KS>
+struct Expm1 {
+    static __device__ __forceinline__ void run(const double (&x)[1 << KS], double (&r)[1 << KS])
+    {
+        constexpr int H = 1 << (KS - 1);
+        double x0[H], x1[H], r0[H], r1[H], e0[H], p[H];
+#pragma unroll
+        for (int W = 0; W < H; ++W) {
+            x0[W] = x[W];
+            x1[W] = x[W + H];
+        }
+        Expm1<KS - 1>::run(x0, r0);
+        Expm1<KS - 1>::run(x1, r1);
+#pragma unroll
+        for (int W = 0; W < H; ++W) e0[W] = r0[W];
+        e0[0] += 1.0;
+        mul<KS - 1>(e0, r1, p);
+#pragma unroll
+        for (int W = 0; W < H; ++W) {
+            r[W] = r0[W];
+            r[W + H] = p[W];
+        }
+    }
+};
+
+template <>
+struct Expm1<0> {
+    static __device__ __forceinline__ void run(const double (&x)[1], double (&r)[1])
+    {
+        r[0] = expm1(x[0]);
+    }
+};
+
+// r = exp(x)
+template <int KS>
+__device__ __forceinline__ void exp(const double (&x)[1 << KS], double (&r)[1 << KS])
+{
+    constexpr int N = 1 << KS;
+    double y[N], e[N];
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y) y[Y] = x[Y];
+    y[0] = 0.0;
+    Expm1<KS>::run(y, e);
+    const double s = ::exp(x[0]);
+    e[0] += 1.0;
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y) r[Y] = s * e[Y];
+}
+
+} // namespace mobius

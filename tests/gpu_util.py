@@ -1,0 +1,74 @@
+"""Shared helpers of the GPU tests: run a problem through libqmc and the
+oracle on identical lattice and shifts, compare sector by sector."""
+
+import numpy as np
+
+from oracle import qmc as oq
+from oracle.decompose import decompose as odec
+from paper_1508_02512_amd import frontend as fe
+from paper_1508_02512_amd import qmc
+from seeded_inputs.lattice import lattice
+from seeded_inputs.problems import PROBLEMS
+from seeded_inputs.rng import shift_table
+
+_CTX = None
+
+
+def ctx():
+    global _CTX
+    if _CTX is None:
+        import torch
+        assert torch.cuda.is_available()
+        _CTX = qmc.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    return _CTX
+
+
+def gpu_plan(name, eps_hi=0, lam=0.0, r=2, ppl=0, precision=qmc.QMC_FP64):
+    secs, info = fe.decompose(PROBLEMS[name])
+    plan = ctx().plan(fe.sector_arrays(secs, info), info, eps_hi,
+                      fe.prefactor_series(info, 12), lam=lam, korobov_r=r,
+                      points_per_lane=ppl, precision=precision)
+    return plan, info
+
+
+def sample_sectors(name, per_class=8, kin=None):
+    """All sectors with at most one pole plus up to `per_class` evenly spaced
+    sectors of every higher pole count."""
+    osecs, _ = odec(PROBLEMS[name])
+    poles = [sum(1 for a in s["a"] if a == -1) for s in osecs]
+    out = [i for i, k in enumerate(poles) if k <= 1]
+    for k in sorted(set(poles)):
+        if k <= 1:
+            continue
+        idx = [i for i, kk in enumerate(poles) if kk == k]
+        step = max(1, len(idx) // per_class)
+        out += idx[::step][:per_class]
+    return sorted(out)
+
+
+def compare_sectors(name, kin, n, m, eps_hi=0, lam=0.0, r=2, ppl=0, tol=1e-12,
+                    sectors=None, seed=0, quad_from=2):
+    """Max over (sector, shift, order) of |gpu - oracle| / sum|terms|.
+
+    Sectors with at least `quad_from` poles are compared with the oracle's
+    binary128 build: the mixed differences of Eq. 11 amplify the FP64
+    oracle's own rounding beyond the parity bar there."""
+    plan, info = gpu_plan(name, eps_hi, lam, r, ppl)
+    z = lattice(n)
+    shifts = shift_table(seed, m, 8)
+    res = plan.integrate(fe.kin_vector(info, kin), (n, z), shifts, sector_sums=True)
+    osecs, oinfo = odec(PROBLEMS[name])
+    idx = range(len(osecs)) if sectors is None else sectors
+    worst = 0.0
+    for s in idx:
+        ns = oq.NumericSector(osecs[s], oinfo, kin)
+        sums, abss, _ = oq.sector_sums(ns, n, z, shifts, r, lam, res["sec_lo"],
+                                       plan.info.sec_orders, quad=ns.nJ >= quad_from)
+        gpu = res["sector_sums"][0, s]
+        scale = abss[..., 0] + abss[..., 1]
+        err = np.abs(gpu - sums)
+        rel = np.where(scale > 0, err / np.where(scale > 0, scale, 1), err)
+        worst = max(worst, float(rel.max()))
+    plan.close()
+    assert worst <= tol, f"{name}: worst relative difference {worst:.3e} > {tol:.0e}"
+    return res, worst
