@@ -121,6 +121,15 @@ class NumericSector:
         return s
 
 
+def effective_lambda(ns: NumericSector, lam):
+    """Deformation parameter used for a sector at its kinematic point.
+
+    Eq. 14 is needed only where F can vanish inside the cube: when every
+    coefficient of the sector's F is non-negative (its constant term is
+    positive) F > 0 on the whole cube and the undeformed contour is used."""
+    return float(lam) if np.any(ns.cF < 0.0) else 0.0
+
+
 def sector_sums(ns: NumericSector, n, z, shifts, r=2, lam=0.0,
                 out_lo=0, out_len=1, nthreads=0, quad=False):
     """(sums, abss, counts): sums[m][out_len] complex = sum_i w g (no 1/n).
@@ -227,7 +236,8 @@ def integrate(problem, kin, n, z, shifts, r=2, lam=0.0, eps_hi=0, nthreads=0,
     per = []
     counts = np.zeros(3, dtype=np.int64)
     for ns in nums:
-        S, _, c = sector_sums(ns, n, z, shifts, r, lam, sec_lo, K, nthreads, quad)
+        S, _, c = sector_sums(ns, n, z, shifts, r, effective_lambda(ns, lam), sec_lo, K,
+                              nthreads, quad)
         per.append(S)
         counts += c.sum(axis=0)
     eps_lo = sec_lo + pref_lo

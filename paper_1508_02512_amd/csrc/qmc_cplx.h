@@ -1,0 +1,402 @@
+// Integrand kernel with contour deformation (Section II, Eq. 14) for the
+// physical region: every variable is deformed as
+//     z_j = t_j - i lambda t_j (1 - t_j) dF/dt_j(t) = t_j phi_j,
+// the Jacobian det(dz/dt) multiplies the integrand, and the sector integrand
+// of Eq. 9 becomes
+//     det J prod_j t_j^(a_j + b_j eps) phi_j^(a_j + b_j eps) U(z)^(u0+u1 eps) F(z)^(f0+f1 eps).
+// F carries -i0: its logarithm takes the branch -i pi where F is real and
+// negative.  Points where Im F(z) > 0 or Re U(z) <= 0 are counted as sign
+// violations.  The pole subtraction of Eq. 11 uses the corner values of the
+// deformed integrand (the deformation vanishes on t_j = 0 in z_j but not
+// in the other variables, so every corner is a full evaluation).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qmc_common.h"
+#include "qmc_device.h"
+#include "qmc_kernels.h"
+
+namespace qmc_cplx {
+
+using namespace qmc;
+
+struct cd {
+    double r, i;
+};
+
+__device__ __forceinline__ cd cmul(cd a, cd b)
+{
+    return {fma(a.r, b.r, -a.i * b.i), fma(a.r, b.i, a.i * b.r)};
+}
+
+__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ cd cscale(cd a, double s) { return {a.r * s, a.i * s}; }
+
+__device__ __forceinline__ cd crecip(cd a)
+{
+    const double inv = 1.0 / fma(a.r, a.r, a.i * a.i);
+    return {a.r * inv, -a.i * inv};
+}
+
+__device__ __forceinline__ cd cpowi(cd x, int e)
+{
+    cd r = {1.0, 0.0};
+    const int a = e < 0 ? -e : e;
+    for (int k = 0; k < a; ++k) r = cmul(r, x);
+    return e < 0 ? crecip(r) : r;
+}
+
+// principal logarithm; a real negative argument takes -i pi (the -i0 side)
+__device__ __forceinline__ cd clog_m(cd x)
+{
+    const double m = 0.5 * log(fma(x.r, x.r, x.i * x.i));
+    double a = atan2(x.i, x.r);
+    if (x.i == 0.0 && x.r < 0.0) a = -M_PI;
+    return {m, a};
+}
+
+__device__ __forceinline__ cd cexp_(cd x)
+{
+    const double e = exp(x.r);
+    double s, c;
+    sincos(x.i, &s, &c);
+    return {e * c, e * s};
+}
+
+template <int DM>
+__device__ __forceinline__ cd cmonomial(uint32_t e, const cd *z, const cd *z2, const cd *z3)
+{
+    cd v = {1.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        const uint32_t ej = (e >> (4 * j)) & 15u;
+        if (ej == 0u) continue;
+        if (ej == 1u) {
+            v = cmul(v, z[j]);
+        } else if (ej == 2u) {
+            v = cmul(v, z2[j]);
+        } else if (ej == 3u) {
+            v = cmul(v, z3[j]);
+        } else {
+            cd p = cmul(z2[j], z2[j]);
+            for (uint32_t k = 4u; k < ej; ++k) p = cmul(p, z[j]);
+            v = cmul(v, p);
+        }
+    }
+    return v;
+}
+
+template <int DM>
+__device__ __forceinline__ double rmonomial(uint32_t e, const double *t, const double *t2,
+                                            const double *t3)
+{
+    double v = 1.0;
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        const uint32_t ej = (e >> (4 * j)) & 15u;
+        if (ej == 0u) continue;
+        if (ej == 1u) {
+            v *= t[j];
+        } else if (ej == 2u) {
+            v *= t2[j];
+        } else if (ej == 3u) {
+            v *= t3[j];
+        } else {
+            double p = t2[j] * t2[j];
+            for (uint32_t k = 4u; k < ej; ++k) p *= t[j];
+            v *= p;
+        }
+    }
+    return v;
+}
+
+template <int DM, int KS, int K>
+struct CplxPoint {
+    double t[DM], omt[DM], lt[DM];
+    double invt[KS > 0 ? KS : 1];
+    double E[KS > 0 ? KS : 1][K];   // (b_j ln t_j)^r / r! of the pole variables
+    double LN;                       // sum_{j >= ks} b_j ln t_j
+    const double *coef;              // U, F coefficients at this point
+    const double *dcoef;             // derivative coefficients at this point
+    const uint32_t *texp, *dexp;
+    int bad;
+};
+
+// h at corner X (pole variables in X set to 0), deformed, as a series
+template <int DM, int KS, int K>
+__device__ __forceinline__ void leaf(const qmc_sec_dev *S, CplxPoint<DM, KS, K> &P, int X,
+                                     cd (&h)[K])
+{
+    double tp[DM], op[DM], tp2[DM], tp3[DM];
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        const bool zero = j < KS && ((X >> j) & 1);
+        tp[j] = zero ? 0.0 : P.t[j];
+        op[j] = zero ? 1.0 : P.omt[j];
+        tp2[j] = tp[j] * tp[j];
+        tp3[j] = tp2[j] * tp[j];
+    }
+    const int d = S->dim;
+    const double lam = S->lambda;
+    // gradient and Hessian of F at the real point
+    double g[DM], H[DM][DM];
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        double s = 0.0;
+        if (j < d)
+            for (int q = S->d1[j]; q < S->d1[j + 1]; ++q)
+                s = fma(P.dcoef[q], rmonomial<DM>(P.dexp[q], tp, tp2, tp3), s);
+        g[j] = s;
+    }
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+#pragma unroll
+        for (int k = j; k < DM; ++k) {
+            double s = 0.0;
+            if (k < d) {
+                const int idx = j * QMC_DMAX - j * (j - 1) / 2 + (k - j);
+                for (int q = S->d2[idx]; q < S->d2[idx + 1]; ++q)
+                    s = fma(P.dcoef[q], rmonomial<DM>(P.dexp[q], tp, tp2, tp3), s);
+            }
+            H[j][k] = s;
+            H[k][j] = s;
+        }
+    }
+    // phi_j = 1 - i lambda (1 - t_j) g_j, z_j = t_j phi_j
+    cd phi[DM], z[DM], z2[DM], z3[DM];
+    double qv[DM];
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        qv[j] = lam * op[j] * g[j];
+        phi[j] = {1.0, -qv[j]};
+        z[j] = {tp[j], -tp[j] * qv[j]};
+        z2[j] = cmul(z[j], z[j]);
+        z3[j] = cmul(z2[j], z[j]);
+    }
+    // Jacobian J = I + i M, M_jk = -lambda (delta_jk (1 - 2 t_j) g_j + t_j (1 - t_j) H_jk);
+    // rows beyond the sector's dimension are identity.  Its Hermitian part
+    // after a diagonal similarity is the identity, so elimination without
+    // pivoting is stable.
+    cd J[DM][DM];
+#pragma unroll
+    for (int j = 0; j < DM; ++j)
+#pragma unroll
+        for (int k = 0; k < DM; ++k) {
+            double m = 0.0;
+            if (j < d && k < d) {
+                m = -lam * tp[j] * op[j] * H[j][k];
+                if (j == k) m -= lam * (op[j] - tp[j]) * g[j];
+            }
+            J[j][k] = {j == k ? 1.0 : 0.0, m};
+        }
+    cd det = {1.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < DM; ++c) {
+        det = cmul(det, J[c][c]);
+        const cd inv = crecip(J[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < DM; ++r) {
+            const cd f = cmul(J[r][c], inv);
+#pragma unroll
+            for (int k = c + 1; k < DM; ++k) J[r][k] = csub(J[r][k], cmul(f, J[c][k]));
+        }
+    }
+    // U(z), F(z)
+    cd U = {0.0, 0.0}, F = {0.0, 0.0};
+    for (int q = S->um[0]; q < S->um[QMC_NMASK]; ++q) {
+        const cd v = cmonomial<DM>(P.texp[q], z, z2, z3);
+        U.r = fma(P.coef[q], v.r, U.r);
+        U.i = fma(P.coef[q], v.i, U.i);
+    }
+    for (int q = S->fm[0]; q < S->fm[QMC_NMASK]; ++q) {
+        const cd v = cmonomial<DM>(P.texp[q], z, z2, z3);
+        F.r = fma(P.coef[q], v.r, F.r);
+        F.i = fma(P.coef[q], v.i, F.i);
+    }
+    P.bad |= (F.i > 0.0) | !(U.r > 0.0);
+    const cd lU = clog_m(U), lF = clog_m(F);
+    cd pre;
+    if (S->u0i != QMC_NO_INT && S->f0i != QMC_NO_INT)
+        pre = cmul(cpowi(U, S->u0i), cpowi(F, S->f0i));
+    else
+        pre = cexp_(cadd(cscale(lU, S->u0), cscale(lF, S->f0)));
+    pre = cmul(pre, det);
+    cd L = cadd(cscale(lU, S->u1), cscale(lF, S->f1));
+    L.r += P.LN;
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        if (j >= d || qv[j] == 0.0) continue;
+        // Log phi_j = 1/2 log(1 + q^2) - i atan(q)
+        const cd lphi = {0.5 * log1p(qv[j] * qv[j]), -atan(qv[j])};
+        L = cadd(L, cscale(lphi, S->b[j]));
+        const int ai = j < KS ? -1 : S->aint[j];
+        if (ai == QMC_NO_INT)
+            pre = cmul(pre, cexp_(cscale(lphi, S->a[j])));
+        else if (ai != 0)
+            pre = cmul(pre, cpowi(phi[j], ai));
+    }
+    h[0] = pre;
+#pragma unroll
+    for (int q = 1; q < K; ++q) h[q] = cscale(cmul(h[q - 1], L), 1.0 / q);
+}
+
+template <int K>
+__device__ __forceinline__ void cfold(cd (&A)[K], const cd (&B)[K], double invb, double invt,
+                                      const double (&E)[K])
+{
+    cd D[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) D[q] = csub(A[q], B[q]);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int r = 0; r < q; ++r) {
+            sr = fma(E[r], D[q - 1 - r].r, sr);
+            si = fma(E[r], D[q - 1 - r].i, si);
+        }
+        A[q] = {fma(B[q].r, invb, invt * sr), fma(B[q].i, invb, invt * si)};
+    }
+}
+
+template <int LEVEL, int XB, int DM, int KS, int K>
+struct CTree {
+    static __device__ __forceinline__ void run(const qmc_sec_dev *S, CplxPoint<DM, KS, K> &P,
+                                               cd (&out)[K])
+    {
+        cd B[K];
+        CTree<LEVEL - 1, XB, DM, KS, K>::run(S, P, out);
+        CTree<LEVEL - 1, XB | (1 << (LEVEL - 1)), DM, KS, K>::run(S, P, B);
+        cfold<K>(out, B, S->inv_b[LEVEL - 1], P.invt[LEVEL - 1], P.E[LEVEL - 1]);
+    }
+};
+
+template <int XB, int DM, int KS, int K>
+struct CTree<0, XB, DM, KS, K> {
+    static __device__ __forceinline__ void run(const qmc_sec_dev *S, CplxPoint<DM, KS, K> &P,
+                                               cd (&out)[K])
+    {
+        leaf<DM, KS, K>(S, P, XB, out);
+    }
+};
+
+template <int DM, int KS, int K>
+__global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
+{
+    const int item_id = A.item_begin + (int)blockIdx.x;
+    if (item_id >= A.item_end) return;
+    const qmc_item it = A.items[item_id];
+    const qmc_sec_dev *S = A.sec + it.sector;
+    const qmc_lat_dev *L = A.lat + it.sector;
+    const int d = S->dim;
+    const uint32_t n = L->n;
+    const double inv_n = L->inv_n;
+    const double *shift = A.shifts + it.shift * QMC_DMAX;
+    const int r = A.korobov_r;
+
+    uint32_t l[DM], step[DM];
+    double dl[DM];
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        l[j] = 0u;
+        step[j] = 0u;
+        dl[j] = 0.0;
+        if (j < d) {
+            const uint64_t zz = L->z[j];
+            l[j] = (uint32_t)(((uint64_t)(it.start + threadIdx.x) * zz) % n);
+            step[j] = (uint32_t)(((uint64_t)QMC_BLOCK * zz) % n);
+            dl[j] = shift[S->perm[j]];
+        }
+    }
+    double acc[2][K], cmp[2][K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[0][q] = acc[1][q] = cmp[0][q] = cmp[1][q] = 0.0;
+    int viol = 0;
+
+    for (int p = 0; p < A.ppl; ++p) {
+        const uint32_t off = threadIdx.x + (uint32_t)p * QMC_BLOCK;
+        if (off < it.count) {
+            CplxPoint<DM, KS, K> P;
+            P.coef = A.tcoef + (size_t)it.point * A.n_terms;
+            P.dcoef = A.dcoef + (size_t)it.point * A.n_dterms;
+            P.texp = A.texp;
+            P.dexp = A.dexp;
+            P.bad = 0;
+            double w = 1.0;
+            bool skip = false;
+#pragma unroll
+            for (int j = 0; j < DM; ++j) {
+                P.t[j] = 1.0;
+                P.omt[j] = 0.0;
+                if (j < d) {
+                    double y = fma((double)l[j], inv_n, dl[j]);
+                    if (y >= 1.0) y -= 1.0;
+                    double wj;
+                    korobov(r, y, P.t[j], P.omt[j], wj);
+                    w *= wj;
+                    skip |= (P.t[j] == 0.0);
+                }
+            }
+            if (!(w == 0.0 || skip)) {
+                double pn = 1.0, LN = 0.0;
+#pragma unroll
+                for (int j = 0; j < DM; ++j) {
+                    P.lt[j] = 0.0;
+                    if (j < d) {
+                        const bool pole = j < KS;
+                        const double lt = log(P.t[j]);
+                        P.lt[j] = lt;
+                        const double bj = S->b[j];
+                        if (pole) {
+                            P.invt[pole ? j : 0] = 1.0 / P.t[j];
+                            const double x = bj * lt;
+                            P.E[pole ? j : 0][0] = 1.0;
+#pragma unroll
+                            for (int q = 1; q < K; ++q)
+                                P.E[pole ? j : 0][q] = P.E[pole ? j : 0][q - 1] * x * (1.0 / q);
+                        } else {
+                            LN = fma(bj, lt, LN);
+                            if (S->aint[j] == QMC_NO_INT) pn *= exp(S->a[j] * lt);
+                            else
+                                for (int k = 0; k < S->aint[j]; ++k) pn *= P.t[j];
+                        }
+                    }
+                }
+                P.LN = LN;
+                cd g[K];
+                CTree<KS, 0, DM, KS, K>::run(S, P, g);
+                if (P.bad) {
+                    viol += 1;
+                } else {
+                    const double wp = w * pn;
+#pragma unroll
+                    for (int q = 0; q < K; ++q) {
+                        neumaier(acc[0][q], cmp[0][q], wp * g[q].r);
+                        neumaier(acc[1][q], cmp[1][q], wp * g[q].i);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < DM; ++j) {
+            if (j < d) {
+                const uint32_t v = l[j] + step[j];
+                l[j] = v >= n ? v - n : v;
+            }
+        }
+    }
+    double *dst = A.partial + (size_t)item_id * A.kstride * 4;
+    block_reduce_store<K, 2>(acc, cmp, dst, A.kstride);
+    store_violations(viol, A.viol + item_id);
+}
+
+} // namespace qmc_cplx
+
+#define QMC_CPLX_CASE(DM, KS, KB)                                                  \
+    if (ks == KS && kb == KB) {                                                    \
+        hipLaunchKernelGGL((qmc_cplx::qmc_eval_cplx<DM, KS, KS + KB>), dim3(grid),  \
+                           dim3(QMC_BLOCK), 0, stream, args);                      \
+        return hipGetLastError();                                                  \
+    }

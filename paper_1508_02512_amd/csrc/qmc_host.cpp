@@ -184,8 +184,8 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
         return set_err(ctx, QMC_EUNSUPPORTED, "korobov_r must be 0..3");
     if (o.precision != QMC_FP64)
         return set_err(ctx, QMC_EUNSUPPORTED, "precision mode %d not available", o.precision);
-    if (!(o.lambda >= 0.0) || o.lambda > 0.0)
-        return set_err(ctx, QMC_EUNSUPPORTED, "contour deformation (lambda > 0) not available");
+    if (!(o.lambda >= 0.0) || !std::isfinite(o.lambda))
+        return set_err(ctx, QMC_EINVAL, "lambda must be finite and >= 0");
 
     auto *plan = new (std::nothrow) qmc_plan();
     if (!plan) return set_err(ctx, QMC_ENOMEM, "host allocation");
@@ -332,6 +332,55 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                 h.term_nnz.push_back(nnz);
             }
         }
+        if (h.deform) {
+            if (!qmc_cplx_supported(S.dim, h.ks, kb)) {
+                delete plan;
+                return set_err(ctx, QMC_EUNSUPPORTED,
+                               "sector %d: deformation supports dim <= 6, at most 2 poles "
+                               "and 1-2 orders above them, 1-3 for dim <= 2 (dim %d, %d poles, %d orders)",
+                               s, S.dim, h.ks, kb);
+            }
+            h.lambda = o.lambda;
+            // dF/dt_j and d2F/dt_j dt_k (permuted variables) as term lists
+            auto add_term = [&](const uint8_t *e, const double *c, int dj, int dk, double fac) {
+                uint8_t ee[QMC_DMAX] = {};
+                for (int v = 0; v < S.dim; ++v) ee[v] = e[perm[v]];
+                if (dj >= 0) ee[dj] -= 1;
+                if (dk >= 0) ee[dk] -= 1;
+                uint32_t packed = 0;
+                int nnz = 0;
+                for (int v = 0; v < S.dim; ++v) {
+                    packed |= (uint32_t)ee[v] << (4 * v);
+                    nnz += ee[v] != 0;
+                }
+                plan->dexp.push_back(packed);
+                for (int i = 0; i < pb->n_inv; ++i) plan->dcoef_rows.push_back(fac * c[i]);
+                h.dterm_nnz.push_back(nnz);
+            };
+            const qmc_poly &F = S.F;
+            for (int j = 0; j <= QMC_DMAX; ++j) {
+                h.d1[j] = (int32_t)plan->dexp.size();
+                if (j >= S.dim || j == QMC_DMAX) continue;
+                for (int a = 0; a < F.n_terms; ++a) {
+                    const uint8_t *e = F.exps + (size_t)a * S.dim;
+                    const int ej = e[perm[j]];
+                    if (ej > 0) add_term(e, F.coef + (size_t)a * pb->n_inv, j, -1, ej);
+                }
+            }
+            int idx = 0;
+            for (int j = 0; j < QMC_DMAX; ++j)
+                for (int k = j; k < QMC_DMAX; ++k, ++idx) {
+                    h.d2[idx] = (int32_t)plan->dexp.size();
+                    if (j >= S.dim || k >= S.dim) continue;
+                    for (int a = 0; a < F.n_terms; ++a) {
+                        const uint8_t *e = F.exps + (size_t)a * S.dim;
+                        const int ej = e[perm[j]], ek = e[perm[k]];
+                        const double fac = j == k ? (double)ej * (ej - 1) : (double)ej * ek;
+                        if (fac != 0.0) add_term(e, F.coef + (size_t)a * pb->n_inv, j, k, fac);
+                    }
+                }
+            h.d2[idx] = (int32_t)plan->dexp.size();
+        }
         h.D = std::complex<double>(S.coef_re, S.coef_im);
         h.flops = sector_flops(h);
         plan->flops_per_point += h.flops;
@@ -346,6 +395,8 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
     int rc = qmc_dev_alloc(ctx, (void **)&plan->d_sec, sizeof(qmc_sec_dev) * ns);
     if (rc == QMC_OK)
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_texp, sizeof(uint32_t) * plan->texp.size());
+    if (rc == QMC_OK && !plan->dexp.empty())
+        rc = qmc_dev_alloc(ctx, (void **)&plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
     if (rc != QMC_OK) {
         qmc_plan_free(plan);
         return rc;
@@ -354,6 +405,9 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                              hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(plan->d_texp, plan->texp.data(), sizeof(uint32_t) * plan->texp.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !plan->dexp.empty())
+        e = hipMemcpy(plan->d_dexp, plan->dexp.data(), sizeof(uint32_t) * plan->dexp.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         qmc_plan_free(plan);
@@ -497,7 +551,18 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
             coef[(size_t)p * nt + t] = c;
         }
     }
-    // work list: class-major (ks), then point, sector, shift, tile
+    const int nd = (int)plan->dexp.size();
+    std::vector<double> dcoef((size_t)n_points * nd);
+    for (int p = 0; p < n_points; ++p) {
+        const double *k = kin + (size_t)p * ni;
+        for (int t = 0; t < nd; ++t) {
+            const double *row = plan->dcoef_rows.data() + (size_t)t * ni;
+            double c = 0.0;
+            for (int i = 0; i < ni; ++i) c += row[i] * k[i];
+            dcoef[(size_t)p * nd + t] = c;
+        }
+    }
+    // work list: class-major (poles, kernel width), then point, sector, shift, tile
     uint64_t total = 0;
     for (int s = 0; s < ns; ++s) total += job->n_per_sector[s];
     total *= (uint64_t)m * n_points;
@@ -513,14 +578,40 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
     const int n_groups = n_points * ns * m;
     std::vector<int32_t> gbeg(n_groups), gend(n_groups);
     std::vector<qmc_item> items;
-    for (int cls = 0; cls <= plan->max_ks; ++cls) {
+    // A sector is deformed at a kinematic point only if some coefficient of
+    // F is negative there; with all coefficients >= 0 (and the constant term
+    // > 0) F is positive on the whole cube and the real kernel applies.
+    std::vector<int> key_of((size_t)n_points * ns);
+    std::vector<std::pair<int, int>> keys;     // (ks, dm or 0 for real) of every class
+    for (int p = 0; p < n_points; ++p)
+        for (int s = 0; s < ns; ++s) {
+            const qmc_sec_host &h = plan->secs[s];
+            bool deform = false;
+            if (h.deform) {
+                const double *c = coef.data() + (size_t)p * nt;
+                for (int q = h.fm[0]; q < h.fm[QMC_NMASK]; ++q) deform |= c[q] < 0.0;
+            }
+            const std::pair<int, int> key{h.ks, deform ? qmc_cplx_dm(h.dim) : 0};
+            auto it = std::find(keys.begin(), keys.end(), key);
+            if (it == keys.end()) {
+                keys.push_back(key);
+                it = keys.end() - 1;
+            }
+            key_of[(size_t)p * ns + s] = (int)(it - keys.begin());
+        }
+    std::vector<int> order(keys.size());
+    for (size_t i = 0; i < keys.size(); ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return keys[x] < keys[y]; });
+    for (int ki : order) {
         qmc_class c{};
-        c.ks = cls;
+        c.ks = keys[ki].first;
+        c.dm = keys[ki].second;
+        c.deform = c.dm != 0;
         c.kb = plan->kb;
         c.begin = (int)items.size();
         for (int p = 0; p < n_points; ++p)
             for (int s = 0; s < ns; ++s) {
-                if (plan->secs[s].ks != cls) continue;
+                if (key_of[(size_t)p * ns + s] != ki) continue;
                 const uint64_t n = job->n_per_sector[s];
                 for (int k = 0; k < m; ++k) {
                     const int g = (p * ns + s) * m + k;
@@ -551,6 +642,7 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
     int rc = QMC_OK;
     if (!rc) rc = job_upload(job, &job->d_lat, lats.data(), lats.size());
     if (!rc) rc = job_upload(job, &job->d_coef, coef.data(), coef.size());
+    if (!rc) rc = job_upload(job, &job->d_dcoef, dcoef.data(), dcoef.size());
     if (!rc) rc = job_upload(job, &job->d_shift, shifts, (size_t)m * QMC_DMAX);
     if (!rc) rc = job_upload(job, &job->d_items, items.data(), items.size());
     if (!rc) rc = job_upload(job, &job->d_gbeg, gbeg.data(), gbeg.size());
@@ -609,7 +701,10 @@ extern "C" int qmc_run(qmc_job *job)
     for (const qmc_class &c : job->classes) {
         A.item_begin = c.begin;
         A.item_end = c.end;
-        HIP_CHECK(ctx, qmc_launch_real(c.ks, c.kb, A, c.end - c.begin, ctx->stream));
+        if (c.deform)
+            HIP_CHECK(ctx, qmc_launch_cplx(c.dm, c.ks, c.kb, A, c.end - c.begin, ctx->stream));
+        else
+            HIP_CHECK(ctx, qmc_launch_real(c.ks, c.kb, A, c.end - c.begin, ctx->stream));
     }
     HIP_CHECK(ctx, hipEventRecord(job->ev1, ctx->stream));
     HIP_CHECK(ctx, qmc_launch_reduce(job->d_partial, job->d_viol, job->d_gbeg, job->d_gend,

@@ -70,7 +70,7 @@ struct qmc_plan {
 };
 
 struct qmc_class {                   // items launched by one kernel instance
-    int ks = 0, kb = 1, deform = 0;
+    int ks = 0, kb = 1, deform = 0, dm = 0;
     int begin = 0, end = 0;
 };
 

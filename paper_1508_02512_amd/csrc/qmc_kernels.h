@@ -10,6 +10,13 @@
 hipError_t qmc_launch_real(int ks, int kb, const qmc_launch_args &args, int grid,
                            hipStream_t stream);
 
+// Complex FP64 integrand with contour deformation (Eq. 14) for sectors of
+// dimension <= dm (dm = qmc_cplx_dm(dim)).
+hipError_t qmc_launch_cplx(int dm, int ks, int kb, const qmc_launch_args &args, int grid,
+                           hipStream_t stream);
+int qmc_cplx_dm(int dim);
+bool qmc_cplx_supported(int dim, int ks, int kb);
+
 // Fixed-order compensated sum of each group's items.
 hipError_t qmc_launch_reduce(const double *partial, const int32_t *viol,
                              const int32_t *group_begin, const int32_t *group_end,

@@ -13,83 +13,11 @@
 #include "qmc_device.h"
 #include "qmc_kernels.h"
 #include "qmc_mobius.h"
+#include "qmc_common.h"
 
 namespace {
 
-// ---------------------------------------------------------------- helpers
-
-__device__ __forceinline__ void neumaier(double &s, double &c, double x)
-{
-    const double t = s + x;
-    c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
-    s = t;
-}
-
-__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
-{
-    s = a + b;
-    const double bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
-// Korobov periodiser of order r: t = psi_r(y), 1 - t = psi_r(1 - y), weight
-// w = y^r (1-y)^r / B(r+1, r+1).  r = 1 is Eq. 21 (3y^2 - 2y^3).
-__device__ __forceinline__ void korobov(int r, double y, double &t, double &omt,
-                                        double &w)
-{
-    const double u = 1.0 - y;
-    if (r == 2) {
-        t = y * y * y * fma(y, fma(6.0, y, -15.0), 10.0);
-        omt = u * u * u * fma(u, fma(6.0, u, -15.0), 10.0);
-        w = 30.0 * (y * u) * (y * u);
-    } else if (r == 1) {
-        t = y * y * fma(-2.0, y, 3.0);
-        omt = u * u * fma(-2.0, u, 3.0);
-        w = 6.0 * y * u;
-    } else if (r == 3) {
-        t = y * y * y * y * fma(y, fma(y, fma(-20.0, y, 70.0), -84.0), 35.0);
-        omt = u * u * u * u * fma(u, fma(u, fma(-20.0, u, 70.0), -84.0), 35.0);
-        const double yu = y * u;
-        w = 140.0 * yu * yu * yu;
-    } else {
-        t = y;
-        omt = u;
-        w = 1.0;
-    }
-}
-
-// prod_j t_j^e_j for exponents packed 4 bits per variable (wave-uniform)
-__device__ __forceinline__ double monomial(uint32_t e, const double *t,
-                                           const double *t2, const double *t3)
-{
-    double v = 1.0;
-#pragma unroll
-    for (int j = 0; j < QMC_DMAX; ++j) {
-        const uint32_t ej = (e >> (4 * j)) & 15u;
-        if (ej == 0u) continue;
-        if (ej == 1u) {
-            v *= t[j];
-        } else if (ej == 2u) {
-            v *= t2[j];
-        } else if (ej == 3u) {
-            v *= t3[j];
-        } else {
-            double p = t2[j] * t2[j];
-            for (uint32_t k = 4u; k < ej; ++k) p *= t[j];
-            v *= p;
-        }
-    }
-    return v;
-}
-
-__device__ __forceinline__ double ipow(double x, int e)
-{
-    // e is wave-uniform; negative powers by one division
-    double r = 1.0;
-    const int a = e < 0 ? -e : e;
-    for (int k = 0; k < a; ++k) r *= x;
-    return e < 0 ? 1.0 / r : r;
-}
+using namespace qmc;
 
 // ------------------------------------------------------- real integrand
 
@@ -165,6 +93,41 @@ struct Tree<0, XB, KS, K> {
     }
 };
 
+// g[q + r + |Y|] += CY[Y] LY[Y]^r / r! h_q^[Y] for every order q of h, with
+// h_{q+1} = h_q B / (q + 1) formed only where it still contributes.
+template <int KS, int K, int Q>
+struct Accum {
+    static __device__ __forceinline__ void run(const qmc_sec_dev *S, const double (&B)[1 << KS],
+                                               double (&T)[1 << KS], const double (&CY)[1 << KS],
+                                               const double (&LY)[1 << KS], double (&g)[K])
+    {
+        constexpr int N = 1 << KS;
+#pragma unroll
+        for (int Y = 0; Y < N; ++Y) {
+            const int pc = __builtin_popcount(Y);
+            if (Q + pc >= K) continue;
+            double e = CY[Y] * T[Y];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const int o = Q + r + pc;
+                if (o < K) {
+                    g[o] += e;
+                    e *= LY[Y] * (1.0 / (r + 1));
+                }
+            }
+        }
+        if constexpr (Q + 1 < K) {
+            constexpr int MAXPC = K - 2 - Q < KS ? K - 2 - Q : KS;
+            double nt[N];
+            mobius::mul<KS, MAXPC>(T, B, nt);
+#pragma unroll
+            for (int Y = 0; Y < N; ++Y)
+                T[Y] = __builtin_popcount(Y) <= MAXPC ? nt[Y] * (1.0 / (Q + 1)) : 0.0;
+            Accum<KS, K, Q + 1>::run(S, B, T, CY, LY, g);
+        }
+    }
+};
+
 // Sectors with two or more poles: the subtraction of Eq. 11 from Moebius
 // coefficients (see qmc_mobius.h).  On entry P.SU, P.SF hold the mask sums
 // of U and F, i.e. their Moebius coefficients.  h = U^(u0+u1 eps)
@@ -216,94 +179,8 @@ __device__ __forceinline__ void stable_series(const qmc_sec_dev *S, RealPoint<KS
     }
 #pragma unroll
     for (int o = 0; o < K; ++o) g[o] = 0.0;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-#pragma unroll
-        for (int Y = 0; Y < N; ++Y) {
-            constexpr int dummy = 0;
-            (void)dummy;
-            const int pc = __builtin_popcount(Y);
-            double e = CY[Y] * T[Y];     // c_Y * (b ln t)^r / r! * h_q^[Y], r = 0
-#pragma unroll
-            for (int r = 0; r < K; ++r) {
-                const int o = q + r + pc;
-                if (o < K) {
-                    g[o] += e;
-                    e *= LY[Y] * (1.0 / (r + 1));
-                }
-            }
-        }
-        if (q + 1 < K) {
-            double nt[N];
-            mobius::mul<KS>(T, B, nt);
-#pragma unroll
-            for (int Y = 0; Y < N; ++Y) T[Y] = nt[Y] * (1.0 / (q + 1));
-        }
-    }
-}
-
-// --------------------------------------------------------- block reduce
-
-template <int K, int NC>
-__device__ __forceinline__ void block_reduce_store(double (&s)[NC][K], double (&c)[NC][K],
-                                                   double *dst, int kstride)
-{
-    __shared__ double red[QMC_BLOCK / 64][NC][K][2];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int p = 0; p < NC; ++p) {
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            double ss = s[p][q], cc = c[p][q];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double os = __shfl_xor(ss, off);
-                const double oc = __shfl_xor(cc, off);
-                double e;
-                two_sum(ss, os, ss, e);
-                cc = cc + oc + e;
-            }
-            if (lane == 0) {
-                red[wave][p][q][0] = ss;
-                red[wave][p][q][1] = cc;
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < kstride) {
-        const int q = threadIdx.x;
-        if (q < K) {
-#pragma unroll
-            for (int p = 0; p < NC; ++p) {
-                double ss = red[0][p][q][0], cc = red[0][p][q][1];
-#pragma unroll
-                for (int w = 1; w < QMC_BLOCK / 64; ++w) {
-                    double e;
-                    two_sum(ss, red[w][p][q][0], ss, e);
-                    cc = cc + red[w][p][q][1] + e;
-                }
-                dst[(size_t)q * 4 + 2 * p] = ss;
-                dst[(size_t)q * 4 + 2 * p + 1] = cc;
-            }
-            if (NC == 1) {
-                dst[(size_t)q * 4 + 2] = 0.0;
-                dst[(size_t)q * 4 + 3] = 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) dst[(size_t)q * 4 + c] = 0.0;
-        }
-    }
-}
-
-__device__ __forceinline__ void store_violations(int viol, int32_t *dst)
-{
-    __shared__ int vsum;
-    if (threadIdx.x == 0) vsum = 0;
-    __syncthreads();
-    if (viol) atomicAdd(&vsum, viol);
-    __syncthreads();
-    if (threadIdx.x == 0) *dst = vsum;
+    // h_q is needed only on subsets with at most K-1-q variables
+    Accum<KS, K, 0>::run(S, B, T, CY, LY, g);
 }
 
 // ------------------------------------------------------------ kernels
@@ -318,7 +195,7 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
     const qmc_lat_dev *L = A.lat + it.sector;
     const int d = S->dim;
     const uint32_t n = L->n;
-    const double dn = (double)n;
+    const double inv_n = L->inv_n;
     const double *coef = A.tcoef + (size_t)it.point * A.n_terms;
     const double *shift = A.shifts + it.shift * QMC_DMAX;
     const int r = A.korobov_r;
@@ -352,7 +229,7 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
             for (int j = 0; j < QMC_DMAX; ++j) {
                 t[j] = 1.0;
                 if (j < d) {
-                    double y = (double)l[j] / dn + dl[j];
+                    double y = fma((double)l[j], inv_n, dl[j]);
                     if (y >= 1.0) y -= 1.0;
                     double omt, wj;
                     korobov(r, y, t[j], omt, wj);

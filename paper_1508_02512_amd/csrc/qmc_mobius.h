@@ -31,14 +31,26 @@ struct Fn {
     double c[N];
 };
 
-// out = f * g (union product)
-template <int KS>
+// reciprocal to ~1 ulp: hardware estimate and two Newton steps
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// out = f * g (union product); only the coefficients with at most MAXPC
+// variables are formed (the others are left untouched)
+template <int KS, int MAXPC = KS>
 __device__ __forceinline__ void mul(const double (&f)[1 << KS], const double (&g)[1 << KS],
                                     double (&out)[1 << KS])
 {
     constexpr int N = 1 << KS;
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) {
+        if (__builtin_popcount(Y) > MAXPC) continue;
         double s = 0.0;
 #pragma unroll
         for (int A = 0; A < N; ++A) {
@@ -85,7 +97,7 @@ __device__ __forceinline__ void div(const double (&a)[1 << KS], const double (&b
                 s = fma(-b[A], q[R | C], s);
             }
         }
-        q[Y] = s / corner<KS>(b, Y);
+        q[Y] = s * rcp(corner<KS>(b, Y));
     }
 }
 
@@ -128,7 +140,7 @@ __device__ __forceinline__ void log(const double (&f)[1 << KS], double (&r)[1 <<
 {
     constexpr int N = 1 << KS;
     double x[N];
-    const double inv0 = 1.0 / f[0];
+    const double inv0 = rcp(f[0]);
     x[0] = 0.0;
 #pragma unroll
     for (int Y = 1; Y < N; ++Y) x[Y] = f[Y] * inv0;

@@ -62,7 +62,8 @@ def compare_sectors(name, kin, n, m, eps_hi=0, lam=0.0, r=2, ppl=0, tol=1e-12,
     worst = 0.0
     for s in idx:
         ns = oq.NumericSector(osecs[s], oinfo, kin)
-        sums, abss, _ = oq.sector_sums(ns, n, z, shifts, r, lam, res["sec_lo"],
+        sums, abss, _ = oq.sector_sums(ns, n, z, shifts, r, oq.effective_lambda(ns, lam),
+                                       res["sec_lo"],
                                        plan.info.sec_orders, quad=ns.nJ >= quad_from)
         gpu = res["sector_sums"][0, s]
         scale = abss[..., 0] + abss[..., 1]

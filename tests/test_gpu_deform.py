@@ -1,0 +1,85 @@
+"""GPU contour deformation (Eq. 14) against the oracle and closed forms."""
+
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import compare_sectors, gpu_plan
+from paper_1508_02512_amd import frontend as fe
+from seeded_inputs.lattice import lattice
+from seeded_inputs.rng import shift_table
+
+pytestmark = pytest.mark.gpu
+
+
+def test_massive_bubble_above_threshold():
+    print("bubble_massive s=4.5 lambda=0.5", flush=True)
+    res, _ = compare_sectors("bubble_massive", {"s": 4.5, "msq": 1.0}, 65521, 4, lam=0.5)
+    want = 1.19173527491182 + 1.04719755119660j
+    got = res["mean"][0, -1]
+    assert abs(got.real - want.real) < 6 * res["err_re"][0, -1] + 1e-9
+    assert abs(got.imag - want.imag) < 6 * res["err_im"][0, -1] + 1e-9
+    assert res["violations"] == 0
+
+
+def test_massless_bubble_negative_constant_f():
+    # F = -s < 0 everywhere: log F = ln|F| - i pi
+    print("bubble s=3 lambda=0.5", flush=True)
+    res, _ = compare_sectors("bubble", {"s": 3.0}, 10007, 3, lam=0.5, eps_hi=1)
+    assert abs(res["mean"][0, 1] - (0.324172046430357 + math.pi * 1j)) < 1e-9
+
+
+def test_box_physical():
+    print("box s=3 t=-2 lambda=0.3", flush=True)
+    res, _ = compare_sectors("box", {"s": 3.0, "t": -2.0}, 10007, 4, lam=0.3)
+    assert res["violations"] == 0
+
+
+@pytest.mark.parametrize("lam", [0.05, 0.1])
+def test_np_vertex_physical(lam):
+    print(f"np_vertex s=4.5 lambda={lam}", flush=True)
+    res, _ = compare_sectors("np_vertex", {"s": 4.5, "msq": 1.0}, 1009, 2, lam=lam)
+    assert res["violations"] == 0
+
+
+def test_np_vertex_lambda_independence():
+    plan1, info = gpu_plan("np_vertex", lam=0.05)
+    plan2, _ = gpu_plan("np_vertex", lam=0.1)
+    args = (fe.kin_vector(info, {"s": 4.5, "msq": 1.0}), (262139, lattice(262139)),
+            shift_table(0, 8, 8))
+    a, b = plan1.integrate(*args), plan2.integrate(*args)
+    err = np.hypot(a["err_re"], a["err_im"]) + np.hypot(b["err_re"], b["err_im"])
+    assert np.all(np.abs(a["mean"] - b["mean"]) < 6 * err + 1e-10)
+    plan1.close()
+    plan2.close()
+
+
+def test_np_vertex_lambda_too_large_is_reported():
+    """lambda = 0.5 pushes Im F(z) above 0 at some points for this integral;
+    the kernel counts them and the call returns QMC_EDEFORM (the oracle
+    counts violations on the same inputs too)."""
+    from oracle import qmc as oq
+    from oracle.decompose import decompose as odec
+    from seeded_inputs.problems import PROBLEMS
+    plan, info = gpu_plan("np_vertex", lam=0.5)
+    kin = {"s": 4.5, "msq": 1.0}
+    res = plan.integrate(fe.kin_vector(info, kin), (1009, lattice(1009)), shift_table(0, 2, 8),
+                         allow_violations=True)
+    assert res["status"] == -6 and res["violations"] > 0
+    osecs, oinfo = odec(PROBLEMS["np_vertex"])
+    bad = 0
+    for s in osecs:
+        _, _, c = oq.sector_sums(oq.NumericSector(s, oinfo, kin), 1009, lattice(1009),
+                                 shift_table(0, 2, 8), 2, 0.5, 0, 1)
+        bad += int(c[:, :2].sum())
+    assert bad > 0
+    plan.close()
+
+
+@pytest.mark.parametrize("s", [-5.0, 6.0, 9.5])
+def test_triangle2l(s):
+    """Below threshold the sectors run undeformed (all F coefficients >= 0)."""
+    print(f"triangle2l s={s}", flush=True)
+    res, _ = compare_sectors("triangle2l", {"s": s, "msq": 1.0}, 1009, 2, lam=0.1)
+    assert res["violations"] == 0
