@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--shifts", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-target", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -70,6 +74,67 @@ def cpu_baseline(target_seconds):
     return {"value": evals / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"planar double box s=-3 t=-1, first {done} of {len(nums)} sectors, "
                       f"n={n}, m={m} shifts, FP64 oracle, {cores} threads"}
+
+
+def serve_bench(qmc, fe, PROBLEMS, lattice, seconds, rate, fp32, slots, log):
+    """Poisson request stream (seeded) mixing the one-loop box, the planar
+    double box and the non-planar vertex at physical kinematics, target
+    1e-3 relative; embedded lattices n = 2^14 .. 2^22 doubling, 8 shifts."""
+    import numpy as np
+
+    rng = np.random.default_rng(0)
+    prec = qmc.QMC_FP32_EVAL if fp32 else qmc.QMC_FP64
+    ctx = qmc.Context(0, max_slots=slots)
+    plans = {}
+    for name, lam in (("box", 0.5), ("doublebox", 0.25), ("np_vertex", 0.5)):
+        secs, info = fe.decompose(PROBLEMS[name])
+        plans[name] = (ctx.plan(fe.sector_arrays(secs, info), info, 0,
+                                fe.prefactor_series(info, 12), lam=lam, precision=prec), info)
+    z = lattice(1 << 24)
+    n_req = int(seconds * rate)
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    kinds = rng.integers(0, 3, size=n_req)
+    reqs = []
+    t0 = time.perf_counter()
+    t_next = t0
+    for i in range(n_req):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
+        if kinds[i] == 2:
+            name = "np_vertex"
+            vals = {"s": float(rng.uniform(4.2, 8.0)), "msq": 1.0}
+        else:
+            name = "box" if kinds[i] == 0 else "doublebox"
+            sv = float(rng.uniform(1.0, 10.0))
+            vals = {"s": sv, "t": float(rng.uniform(-sv + 0.1, -0.1))}
+        plan, info = plans[name]
+        reqs.append((name, qmc.submit(plan, fe.kin_vector(info, vals), 1e-3, 1 << 14, 1 << 22,
+                                      8, 1000 + i, z)))
+    lat, evals, status = [], 0, {}
+    for name, r in reqs:
+        out = r.wait(600)
+        if out is None:
+            status["timeout"] = status.get("timeout", 0) + 1
+            continue
+        lat.append(out["latency_ms"])
+        evals += out["evals"]
+        status[out["rc"]] = status.get(out["rc"], 0) + 1
+        r.release()
+    wall = time.perf_counter() - t0
+    for plan, _ in plans.values():
+        plan.close()
+    ctx.close()
+    lat = np.array(lat)
+    res = {"requests": n_req, "rate_req_s": rate, "slots": slots,
+           "precision": "fp32-eval" if fp32 else "fp64",
+           "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+           "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+           "completed_req_s": len(lat) / wall, "evals_per_s": evals / wall,
+           "wall_s": wall, "status_counts": {str(k): v for k, v in status.items()}}
+    log(f"serve ({res['precision']}, slots {slots}): p50 {res['p50_ms']} ms, "
+        f"p99 {res['p99_ms']} ms, {res['completed_req_s']:.1f} req/s")
+    return res
 
 
 def main():
@@ -118,23 +183,67 @@ def main():
     avg_kernel_s = float(np.mean(kernel_ms)) / 1e3
     achieved = res["algo_flops"] / avg_kernel_s
 
-    # time to 1e-3 relative error: lattice doubling with prime sizes
-    ttt = None
-    if not args.no_time_to_target:
+    def time_to_target(pl, label):
+        """Wall time of the prime-lattice doubling until every order has
+        err/|mean| <= 1e-3 (absolute against the largest order where an
+        order is below 1e-3 of it)."""
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for nn in DOUBLING_PRIMES:
-            r = plan.integrate(kin, (nn, lattice(nn)), shift_table(0, m, 8))
+            r = pl.integrate(kin, (nn, lattice(nn)), shift_table(0, m, 8))
             mean = r["mean"][0]
             err = np.hypot(r["err_re"][0], r["err_im"][0])
             scale = np.abs(mean)
             rel = np.where(scale > 1e-3 * scale.max(), err / np.maximum(scale, 1e-300),
                            err / scale.max())
-            log(f"time-to-target: n={nn} max rel err {float(rel.max()):.2e}")
+            log(f"time-to-target ({label}): n={nn} max rel err {float(rel.max()):.2e}")
             if np.all(rel <= 1e-3):
-                ttt = {"seconds": time.perf_counter() - t1, "n": nn,
-                       "max_rel_err": float(rel.max())}
-                break
+                return {"seconds": time.perf_counter() - t1, "n": nn,
+                        "max_rel_err": float(rel.max())}, r
+        return None, r
+
+    ttt = None
+    if not args.no_time_to_target:
+        ttt, r64 = time_to_target(plan, "fp64")
+
+    # FP32-evaluation mode on the same workload
+    fp32 = None
+    if not args.no_fp32:
+        plan32 = ctx.plan(arrs, info, 0, fe.prefactor_series(info, 12),
+                          precision=qmc.QMC_FP32_EVAL)
+        job32 = plan32.bind(kin, (n, lattice(n)), shift_table(0, m, 8))
+        job32.run()
+        job32.fetch()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        k32 = []
+        for _ in range(args.steps):
+            job32.run()
+            res32 = job32.fetch()
+            k32.append(res32["kernel_ms"])
+        torch.cuda.synchronize()
+        wall32 = time.perf_counter() - t2
+        dev = np.abs(res32["mean"][0] - res["mean"][0]) / np.maximum(
+            np.hypot(res["err_re"][0], res["err_im"][0]), 1e-300)
+        fp32 = {"value": res32["evals"] * args.steps / wall32, "unit": "evals/s",
+                "ms_per_step": wall32 / args.steps * 1e3,
+                "kernel_ms_per_step": float(np.mean(k32)),
+                "achieved_tflops": res32["algo_flops"] / (float(np.mean(k32)) / 1e3) / 1e12,
+                "max_dev_vs_fp64_in_sigma": float(dev.max())}
+        if not args.no_time_to_target:
+            fp32["time_to_1e-3"], _ = time_to_target(plan32, "fp32")
+        job32.close()
+        plan32.close()
+        log(f"fp32: {fp32['value']:.3e} evals/s")
+
+    serve = None
+    if not args.no_serve:
+        serve = {
+            "batched_fp32": serve_bench(qmc, fe, PROBLEMS, lattice, args.serve_seconds,
+                                        args.serve_rate, True, 64, log),
+            "plain_fp64": serve_bench(qmc, fe, PROBLEMS, lattice, args.serve_seconds,
+                                      args.serve_rate, False, 1, log),
+        }
 
     out = {
         "metric": METRIC,
@@ -158,8 +267,8 @@ def main():
                      "kernel_ms_per_step": avg_kernel_s * 1e3,
                      "algo_flops_per_step": res["algo_flops"]},
         "time_to_1e-3": ttt,
-        "fp32_eval": None,
-        "serve": None,
+        "fp32_eval": fp32,
+        "serve": serve,
         "result_eps0": [float(res["mean"][0, -1].real), float(res["err_re"][0, -1])],
     }
     if not args.no_cpu_baseline:

@@ -139,6 +139,9 @@ typedef struct {
     int32_t deform_violations;   /* points with Im F(z) > 0 or Re U(z) <= 0 */
     double kernel_ms;            /* device time of the integrand kernels */
     double algo_flops;           /* algorithmic flops of the integrand kernels */
+    double latency_ms;           /* serving: submit to completion (0 for qmc_integrate) */
+    int32_t steps;               /* serving: lattice sizes evaluated (doublings + 1) */
+    int32_t reserved;
 } qmc_result;
 
 /* Create a context on `device` with at most hbm_budget bytes of device
@@ -177,21 +180,42 @@ int qmc_run(qmc_job *job);
 int qmc_fetch(qmc_job *job, qmc_result *out);
 void qmc_job_free(qmc_job *job);
 
-/* ---- serving (continuous batching) --------------------------------------- */
+/* ---- serving (continuous batching) ---------------------------------------
+ * A request is one integral (a plan) at one kinematic point with a relative
+ * error target.  A scheduler thread owned by the context admits requests
+ * while fewer than max_slots are active and their device memory fits the
+ * HBM budget, and repeatedly launches one batch that advances every active
+ * request by one lattice size: n0 first, then n -> 2n evaluating only the
+ * new (odd) indices of the embedded rank-1 lattice {i z / 2n} (Eq. 17),
+ * whose even indices are the previous lattice.  Per-shift sums stay
+ * resident per request; after each batch the result (Eqs. 19-20) is
+ * checked against the target, and the request completes when every order
+ * has err/|mean| <= target (orders below 1e-3 of the largest are compared
+ * absolutely against the largest), when n_max is reached
+ * (QMC_ENOTCONVERGED), or when it is cancelled.  A request's arithmetic does
+ * not depend on the other requests in the batch, so its result is the
+ * same alone and in the mix. */
 typedef struct {
     const double *kin;           /* [n_inv] one kinematic point */
     double rel_err_target;       /* stop when err/|mean| <= target for every order */
-    uint64_t n0, n_max;          /* embedded lattice sizes (powers of two) */
+    uint64_t n0, n_max;          /* embedded lattice sizes (powers of two, n_max < 2^31) */
     int32_t m;                   /* shifts (>= 2) */
-    uint64_t seed;               /* SplitMix64 seed of the shifts */
-    const uint32_t *z;           /* [QMC_MAX_DIM] odd generating vector for n = 2^k */
+    uint64_t seed;               /* SplitMix64 seed of the shifts (k-major, 53-bit) */
+    const uint32_t *z;           /* [QMC_MAX_DIM] odd generating vector */
 } qmc_request;
 
+/* Queue a request; returns a ticket.  Thread-safe; returns immediately. */
 int qmc_submit(qmc_ctx *ctx, const qmc_plan *plan, const qmc_request *req,
                uint64_t *ticket);
+/* QMC_PENDING while the request runs; its status code when done (the
+ * result is filled, out->coeff sized as for qmc_integrate with one point). */
 int qmc_poll(qmc_ctx *ctx, uint64_t ticket, qmc_result *out);
+/* Block until done or timeout_s elapses (< 0: no timeout). */
 int qmc_wait(qmc_ctx *ctx, uint64_t ticket, double timeout_s, qmc_result *out);
+/* Cancel a queued or running request (it completes with QMC_ECANCELLED). */
 int qmc_cancel(qmc_ctx *ctx, uint64_t ticket);
+/* Release the bookkeeping of a finished request. */
+int qmc_release(qmc_ctx *ctx, uint64_t ticket);
 
 #ifdef __cplusplus
 }

@@ -122,12 +122,17 @@ class NumericSector:
 
 
 def effective_lambda(ns: NumericSector, lam):
-    """Deformation parameter used for a sector at its kinematic point.
+    """Deformation parameter lambda_i of Eq. 14 for a sector at its point.
 
     Eq. 14 is needed only where F can vanish inside the cube: when every
     coefficient of the sector's F is non-negative (its constant term is
-    positive) F > 0 on the whole cube and the undeformed contour is used."""
-    return float(lam) if np.any(ns.cF < 0.0) else 0.0
+    positive) F > 0 on the whole cube and the undeformed contour is used.
+    Otherwise the paper leaves lambda to be chosen; it is taken
+    dimensionless, lam / max |coefficient of F|, so that one value serves
+    all kinematic points and integrals."""
+    if not np.any(ns.cF < 0.0):
+        return 0.0
+    return float(lam) / float(np.max(np.abs(ns.cF)))
 
 
 def sector_sums(ns: NumericSector, n, z, shifts, r=2, lam=0.0,

@@ -121,6 +121,7 @@ struct CplxPoint {
     const double *coef;              // U, F coefficients at this point
     const double *dcoef;             // derivative coefficients at this point
     const uint32_t *texp, *dexp;
+    double lam;                      // deformation parameter of this sector and point
     int bad;
 };
 
@@ -139,7 +140,7 @@ __device__ __forceinline__ void leaf(const qmc_sec_dev *S, CplxPoint<DM, KS, K> 
         tp3[j] = tp2[j] * tp[j];
     }
     const int d = S->dim;
-    const double lam = S->lambda;
+    const double lam = P.lam;
     // gradient and Hessian of F at the real point
     double g[DM], H[DM][DM];
 #pragma unroll
@@ -261,26 +262,40 @@ __device__ __forceinline__ void cfold(cd (&A)[K], const cd (&B)[K], double invb,
     }
 }
 
-template <int LEVEL, int XB, int DM, int KS, int K>
-struct CTree {
-    static __device__ __forceinline__ void run(const qmc_sec_dev *S, CplxPoint<DM, KS, K> &P,
+// All corners of the pole variables in a runtime loop (the deformed leaf is
+// large, so it is instantiated once); partial folds wait on a stack whose
+// levels are unrolled: corner X completes level l when bit l of X is set.
+template <int DM, int KS, int K>
+__device__ __forceinline__ void corners_folded(const qmc_sec_dev *S, CplxPoint<DM, KS, K> &P,
                                                cd (&out)[K])
-    {
-        cd B[K];
-        CTree<LEVEL - 1, XB, DM, KS, K>::run(S, P, out);
-        CTree<LEVEL - 1, XB | (1 << (LEVEL - 1)), DM, KS, K>::run(S, P, B);
-        cfold<K>(out, B, S->inv_b[LEVEL - 1], P.invt[LEVEL - 1], P.E[LEVEL - 1]);
+{
+    cd stack[KS > 0 ? KS : 1][K];
+    for (int X = 0; X < (1 << KS); ++X) {
+        cd cur[K];
+        leaf<DM, KS, K>(S, P, X, cur);
+        bool carry = true;
+#pragma unroll
+        for (int lev = 0; lev < KS; ++lev) {
+            if (!carry) break;
+            if ((X >> lev) & 1) {
+                cd A[K];
+#pragma unroll
+                for (int q = 0; q < K; ++q) A[q] = stack[lev][q];
+                cfold<K>(A, cur, S->inv_b[lev], P.invt[lev], P.E[lev]);
+#pragma unroll
+                for (int q = 0; q < K; ++q) cur[q] = A[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < K; ++q) stack[lev][q] = cur[q];
+                carry = false;
+            }
+        }
+        if (carry) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) out[q] = cur[q];
+        }
     }
-};
-
-template <int XB, int DM, int KS, int K>
-struct CTree<0, XB, DM, KS, K> {
-    static __device__ __forceinline__ void run(const qmc_sec_dev *S, CplxPoint<DM, KS, K> &P,
-                                               cd (&out)[K])
-    {
-        leaf<DM, KS, K>(S, P, XB, out);
-    }
-};
+}
 
 template <int DM, int KS, int K>
 __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
@@ -289,7 +304,7 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
     if (item_id >= A.item_end) return;
     const qmc_item it = A.items[item_id];
     const qmc_sec_dev *S = A.sec + it.sector;
-    const qmc_lat_dev *L = A.lat + it.sector;
+    const qmc_lat_dev *L = A.lat + it.lat;
     const int d = S->dim;
     const uint32_t n = L->n;
     const double inv_n = L->inv_n;
@@ -305,8 +320,8 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
         dl[j] = 0.0;
         if (j < d) {
             const uint64_t zz = L->z[j];
-            l[j] = (uint32_t)(((uint64_t)(it.start + threadIdx.x) * zz) % n);
-            step[j] = (uint32_t)(((uint64_t)QMC_BLOCK * zz) % n);
+            l[j] = (uint32_t)(((uint64_t)(it.start + it.stride * threadIdx.x) * zz) % n);
+            step[j] = (uint32_t)(((uint64_t)QMC_BLOCK * it.stride * zz) % n);
             dl[j] = shift[S->perm[j]];
         }
     }
@@ -315,7 +330,8 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
     for (int q = 0; q < K; ++q) acc[0][q] = acc[1][q] = cmp[0][q] = cmp[1][q] = 0.0;
     int viol = 0;
 
-    for (int p = 0; p < A.ppl; ++p) {
+    const int np = (int)((it.count + QMC_BLOCK - 1) / QMC_BLOCK);
+    for (int p = 0; p < np; ++p) {
         const uint32_t off = threadIdx.x + (uint32_t)p * QMC_BLOCK;
         if (off < it.count) {
             CplxPoint<DM, KS, K> P;
@@ -323,6 +339,7 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
             P.dcoef = A.dcoef + (size_t)it.point * A.n_dterms;
             P.texp = A.texp;
             P.dexp = A.dexp;
+            P.lam = A.lam[(size_t)it.point * A.n_sec + it.sector];
             P.bad = 0;
             double w = 1.0;
             bool skip = false;
@@ -366,7 +383,7 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
                 }
                 P.LN = LN;
                 cd g[K];
-                CTree<KS, 0, DM, KS, K>::run(S, P, g);
+                corners_folded<DM, KS, K>(S, P, g);
                 if (P.bad) {
                     viol += 1;
                 } else {

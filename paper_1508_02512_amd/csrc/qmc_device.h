@@ -43,15 +43,17 @@ struct qmc_lat_dev {         // lattice of one sector, components permuted
     double inv_n;
 };
 
-// One work item: a tile of consecutive lattice indices of one
-// (kinematic point, sector, shift) group.
+// One work item: a tile of lattice indices start, start + stride, ... of
+// one (kinematic point, sector, shift) group.
 struct qmc_item {
-    int32_t sector;
-    int32_t point;
-    int32_t shift;
+    int32_t sector;          // sector header
+    int32_t point;           // row of the contracted coefficients (and of lam)
+    int32_t shift;           // row of the shift table
     int32_t group;           // output group (point, sector, shift)
+    int32_t lat;             // lattice (n, z) of this item
     uint32_t start;          // first lattice index
-    uint32_t count;          // number of indices (<= QMC_BLOCK * ppl)
+    uint32_t count;          // number of indices; each lane takes ceil(count / 256)
+    uint32_t stride;         // 1, or 2 for the odd indices of a doubled lattice
 };
 
 struct qmc_launch_args {
@@ -62,13 +64,14 @@ struct qmc_launch_args {
     const uint32_t *dexp;    // [n_dterms] packed exponents of derivative terms
     const double *dcoef;     // [n_points][n_dterms]
     const double *shifts;    // [m][QMC_DMAX]
+    const double *lam;       // [points][n_sec] deformation parameter per sector
     const qmc_item *items;
     double *partial;         // [n_items][kstride][4]: (s_re, c_re, s_im, c_im)
     int32_t *viol;           // [n_items] deformation / sign violations
     int32_t n_terms, n_dterms;
     int32_t item_begin, item_end;
     int32_t kstride;         // order slots per item in `partial`
-    int32_t ppl;             // lattice points per lane per item
+    int32_t pad0;
     int32_t korobov_r;
-    int32_t pad;
+    int32_t n_sec;
 };

@@ -42,6 +42,20 @@ static int set_err(qmc_ctx *ctx, int code, const char *fmt, ...)
     return code;
 }
 
+int qmc_set_error(qmc_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        std::lock_guard<std::mutex> g(ctx->err_mu);
+        ctx->last_error = buf;
+    }
+    return code;
+}
+
 #define HIP_CHECK(ctx, expr)                                                      \
     do {                                                                          \
         hipError_t e_ = (expr);                                                   \
@@ -182,8 +196,8 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
     if (opts) o = *opts;
     if (o.korobov_r < 0 || o.korobov_r > 3)
         return set_err(ctx, QMC_EUNSUPPORTED, "korobov_r must be 0..3");
-    if (o.precision != QMC_FP64)
-        return set_err(ctx, QMC_EUNSUPPORTED, "precision mode %d not available", o.precision);
+    if (o.precision != QMC_FP64 && o.precision != QMC_FP32_EVAL)
+        return set_err(ctx, QMC_EINVAL, "unknown precision mode %d", o.precision);
     if (!(o.lambda >= 0.0) || !std::isfinite(o.lambda))
         return set_err(ctx, QMC_EINVAL, "lambda must be finite and >= 0");
 
@@ -336,8 +350,9 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
             if (!qmc_cplx_supported(S.dim, h.ks, kb)) {
                 delete plan;
                 return set_err(ctx, QMC_EUNSUPPORTED,
-                               "sector %d: deformation supports dim <= 6, at most 2 poles "
-                               "and 1-2 orders above them, 1-3 for dim <= 2 (dim %d, %d poles, %d orders)",
+                               "sector %d: deformation supports dim <= 6 with at most 4 poles "
+                               "and 1-2 orders above them (dim <= 2: 2 poles, 1-3 orders); "
+                               "got dim %d, %d poles, %d orders",
                                s, S.dim, h.ks, kb);
             }
             h.lambda = o.lambda;
@@ -474,6 +489,54 @@ extern "C" int qmc_plan_get_info(const qmc_plan *plan, qmc_plan_info *info)
 
 // ------------------------------------------------------------------ jobs
 
+void qmc_contract(const qmc_plan *plan, const double *kin, double *coef, double *dcoef)
+{
+    const int ni = plan->n_inv;
+    for (int t = 0; t < plan->n_terms; ++t) {
+        const double *row = plan->tcoef_rows.data() + (size_t)t * ni;
+        double c = 0.0;
+        for (int i = 0; i < ni; ++i) c += row[i] * kin[i];
+        coef[t] = c;
+    }
+    const int nd = (int)plan->dexp.size();
+    for (int t = 0; t < nd; ++t) {
+        const double *row = plan->dcoef_rows.data() + (size_t)t * ni;
+        double c = 0.0;
+        for (int i = 0; i < ni; ++i) c += row[i] * kin[i];
+        dcoef[t] = c;
+    }
+}
+
+// A sector is deformed at a kinematic point only if some coefficient of its
+// F is negative there; with all coefficients >= 0 (and the constant term
+// > 0) F is positive on the whole cube and the real kernel applies.  The
+// deformation parameter is made dimensionless by the largest |coefficient|
+// of the sector's F at that point: lambda_eff = lambda / max |c|.
+// Returns the complex kernel width (0 for the real kernel).
+int qmc_sector_mode(const qmc_plan *plan, int s, const double *coef, double *lam)
+{
+    const qmc_sec_host &h = plan->secs[s];
+    *lam = 0.0;
+    if (!h.deform) return 0;
+    bool deform = false;
+    double cmax = 0.0;
+    for (int q = h.fm[0]; q < h.fm[QMC_NMASK]; ++q) {
+        deform |= coef[q] < 0.0;
+        cmax = std::max(cmax, std::fabs(coef[q]));
+    }
+    if (!deform) return 0;
+    *lam = plan->opts.lambda / cmax;
+    return qmc_cplx_dm(h.dim);
+}
+
+hipError_t qmc_launch_class(const qmc_plan *plan, const qmc_class &c, const qmc_launch_args &A,
+                            hipStream_t stream)
+{
+    if (c.deform) return qmc_launch_cplx(c.dm, c.ks, c.kb, A, c.end - c.begin, stream);
+    return qmc_launch_real(c.ks, c.kb, plan->opts.precision == QMC_FP32_EVAL, A, c.end - c.begin,
+                           stream);
+}
+
 void qmc_job_release(qmc_job *job)
 {
     if (!job) return;
@@ -541,27 +604,11 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
     }
     // coefficients contracted with the kinematics of every point
     const int nt = plan->n_terms, ni = plan->n_inv;
-    std::vector<double> coef((size_t)n_points * nt);
-    for (int p = 0; p < n_points; ++p) {
-        const double *k = kin + (size_t)p * ni;
-        for (int t = 0; t < nt; ++t) {
-            const double *row = plan->tcoef_rows.data() + (size_t)t * ni;
-            double c = 0.0;
-            for (int i = 0; i < ni; ++i) c += row[i] * k[i];
-            coef[(size_t)p * nt + t] = c;
-        }
-    }
     const int nd = (int)plan->dexp.size();
-    std::vector<double> dcoef((size_t)n_points * nd);
-    for (int p = 0; p < n_points; ++p) {
-        const double *k = kin + (size_t)p * ni;
-        for (int t = 0; t < nd; ++t) {
-            const double *row = plan->dcoef_rows.data() + (size_t)t * ni;
-            double c = 0.0;
-            for (int i = 0; i < ni; ++i) c += row[i] * k[i];
-            dcoef[(size_t)p * nd + t] = c;
-        }
-    }
+    std::vector<double> coef((size_t)n_points * nt), dcoef((size_t)n_points * nd);
+    for (int p = 0; p < n_points; ++p)
+        qmc_contract(plan, kin + (size_t)p * ni, coef.data() + (size_t)p * nt,
+                     dcoef.data() + (size_t)p * nd);
     // work list: class-major (poles, kernel width), then point, sector, shift, tile
     uint64_t total = 0;
     for (int s = 0; s < ns; ++s) total += job->n_per_sector[s];
@@ -578,20 +625,14 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
     const int n_groups = n_points * ns * m;
     std::vector<int32_t> gbeg(n_groups), gend(n_groups);
     std::vector<qmc_item> items;
-    // A sector is deformed at a kinematic point only if some coefficient of
-    // F is negative there; with all coefficients >= 0 (and the constant term
-    // > 0) F is positive on the whole cube and the real kernel applies.
     std::vector<int> key_of((size_t)n_points * ns);
+    std::vector<double> lam((size_t)n_points * ns, 0.0);
     std::vector<std::pair<int, int>> keys;     // (ks, dm or 0 for real) of every class
     for (int p = 0; p < n_points; ++p)
         for (int s = 0; s < ns; ++s) {
-            const qmc_sec_host &h = plan->secs[s];
-            bool deform = false;
-            if (h.deform) {
-                const double *c = coef.data() + (size_t)p * nt;
-                for (int q = h.fm[0]; q < h.fm[QMC_NMASK]; ++q) deform |= c[q] < 0.0;
-            }
-            const std::pair<int, int> key{h.ks, deform ? qmc_cplx_dm(h.dim) : 0};
+            const int dm = qmc_sector_mode(plan, s, coef.data() + (size_t)p * nt,
+                                           &lam[(size_t)p * ns + s]);
+            const std::pair<int, int> key{plan->secs[s].ks, dm};
             auto it = std::find(keys.begin(), keys.end(), key);
             if (it == keys.end()) {
                 keys.push_back(key);
@@ -622,8 +663,10 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
                         it.point = p;
                         it.shift = k;
                         it.group = g;
+                        it.lat = s;
                         it.start = (uint32_t)st;
                         it.count = (uint32_t)std::min<uint64_t>(tile, n - st);
+                        it.stride = 1;
                         items.push_back(it);
                     }
                     gend[g] = (int32_t)items.size();
@@ -643,6 +686,7 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
     if (!rc) rc = job_upload(job, &job->d_lat, lats.data(), lats.size());
     if (!rc) rc = job_upload(job, &job->d_coef, coef.data(), coef.size());
     if (!rc) rc = job_upload(job, &job->d_dcoef, dcoef.data(), dcoef.size());
+    if (!rc) rc = job_upload(job, &job->d_lam, lam.data(), lam.size());
     if (!rc) rc = job_upload(job, &job->d_shift, shifts, (size_t)m * QMC_DMAX);
     if (!rc) rc = job_upload(job, &job->d_items, items.data(), items.size());
     if (!rc) rc = job_upload(job, &job->d_gbeg, gbeg.data(), gbeg.size());
@@ -689,22 +733,20 @@ extern "C" int qmc_run(qmc_job *job)
     A.dexp = plan->d_dexp;
     A.dcoef = job->d_dcoef;
     A.shifts = job->d_shift;
+    A.lam = job->d_lam;
+    A.n_sec = (int32_t)plan->secs.size();
     A.items = job->d_items;
     A.partial = job->d_partial;
     A.viol = job->d_viol;
     A.n_terms = plan->n_terms;
     A.n_dterms = (int32_t)plan->dexp.size();
     A.kstride = plan->kstride;
-    A.ppl = job->ppl;
     A.korobov_r = plan->opts.korobov_r;
     HIP_CHECK(ctx, hipEventRecord(job->ev0, ctx->stream));
     for (const qmc_class &c : job->classes) {
         A.item_begin = c.begin;
         A.item_end = c.end;
-        if (c.deform)
-            HIP_CHECK(ctx, qmc_launch_cplx(c.dm, c.ks, c.kb, A, c.end - c.begin, ctx->stream));
-        else
-            HIP_CHECK(ctx, qmc_launch_real(c.ks, c.kb, A, c.end - c.begin, ctx->stream));
+        HIP_CHECK(ctx, qmc_launch_class(plan, c, A, ctx->stream));
     }
     HIP_CHECK(ctx, hipEventRecord(job->ev1, ctx->stream));
     HIP_CHECK(ctx, qmc_launch_reduce(job->d_partial, job->d_viol, job->d_gbeg, job->d_gend,

@@ -12,6 +12,7 @@
 
 #include "../../include/qmc.h"
 #include "qmc_device.h"
+#include "qmc_kernels.h"
 
 struct qmc_serve_state;
 
@@ -84,7 +85,7 @@ struct qmc_job {
     std::vector<qmc_class> classes;
     std::vector<std::pair<void *, size_t>> bufs;
     qmc_lat_dev *d_lat = nullptr;
-    double *d_coef = nullptr, *d_dcoef = nullptr, *d_shift = nullptr;
+    double *d_coef = nullptr, *d_dcoef = nullptr, *d_shift = nullptr, *d_lam = nullptr;
     qmc_item *d_items = nullptr;
     int32_t *d_gbeg = nullptr, *d_gend = nullptr;
     double *d_partial = nullptr, *d_out = nullptr;
@@ -104,3 +105,8 @@ void qmc_job_release(qmc_job *job);
 int qmc_assemble(const qmc_plan *plan, int n_points, int m, const std::vector<uint64_t> &nsec,
                  const double *gsum, qmc_result *out);
 void qmc_serve_shutdown(qmc_ctx *ctx);
+void qmc_contract(const qmc_plan *plan, const double *kin, double *coef, double *dcoef);
+int qmc_sector_mode(const qmc_plan *plan, int s, const double *coef, double *lam);
+hipError_t qmc_launch_class(const qmc_plan *plan, const qmc_class &c, const qmc_launch_args &A,
+                            hipStream_t stream);
+int qmc_set_error(qmc_ctx *ctx, int code, const char *fmt, ...);

@@ -5,9 +5,10 @@
 
 #include "qmc_device.h"
 
-// Real (Euclidean) FP64 integrand for sectors with `ks` poles carrying
-// ks + kb Laurent orders; one work-group per item in [item_begin, item_end).
-hipError_t qmc_launch_real(int ks, int kb, const qmc_launch_args &args, int grid,
+// Real (Euclidean) integrand for sectors with `ks` poles carrying ks + kb
+// Laurent orders, evaluated in FP64 or FP32; one work-group per item in
+// [item_begin, item_end).
+hipError_t qmc_launch_real(int ks, int kb, bool fp32, const qmc_launch_args &args, int grid,
                            hipStream_t stream);
 
 // Complex FP64 integrand with contour deformation (Eq. 14) for sectors of

@@ -16,22 +16,17 @@
 //   - log(1 + x): splitting off the highest variable j,
 //       log(1 + x)(W + j) - log(1 + x)(W) = log(1 + x_j / (1 + x_0))(W),
 //     which recurses on one variable fewer and ends in scalar log1p.
-// No step subtracts nearly equal quantities, so each coefficient keeps
-// FP64 relative accuracy.  Index Y is a bit mask over the pole variables;
-// all loops are over compile-time masks.
+// No step subtracts nearly equal quantities, so each coefficient keeps the
+// relative accuracy of the working type T (double, or float in the FP32
+// evaluation mode).  Index Y is a bit mask over the pole variables; all
+// loops are over compile-time masks.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace mobius {
 
-template <int KS>
-struct Fn {
-    static constexpr int N = 1 << KS;
-    double c[N];
-};
-
-// reciprocal to ~1 ulp: hardware estimate and two Newton steps
+// reciprocal to ~1 ulp: hardware estimate and Newton steps
 __device__ __forceinline__ double rcp(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
@@ -41,17 +36,24 @@ __device__ __forceinline__ double rcp(double x)
     return fma(r, e, r);
 }
 
+__device__ __forceinline__ float rcp(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
 // out = f * g (union product); only the coefficients with at most MAXPC
 // variables are formed (the others are left untouched)
-template <int KS, int MAXPC = KS>
-__device__ __forceinline__ void mul(const double (&f)[1 << KS], const double (&g)[1 << KS],
-                                    double (&out)[1 << KS])
+template <int KS, int MAXPC = KS, typename T>
+__device__ __forceinline__ void mul(const T (&f)[1 << KS], const T (&g)[1 << KS],
+                                    T (&out)[1 << KS])
 {
     constexpr int N = 1 << KS;
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) {
         if (__builtin_popcount(Y) > MAXPC) continue;
-        double s = 0.0;
+        T s = 0;
 #pragma unroll
         for (int A = 0; A < N; ++A) {
             if ((A & ~Y) != 0) continue;
@@ -67,10 +69,10 @@ __device__ __forceinline__ void mul(const double (&f)[1 << KS], const double (&g
 }
 
 // corner value f(Y) = sum_{A subset Y} f^[A]
-template <int KS>
-__device__ __forceinline__ double corner(const double (&f)[1 << KS], int Y)
+template <int KS, typename T>
+__device__ __forceinline__ T corner(const T (&f)[1 << KS], int Y)
 {
-    double s = 0.0;
+    T s = 0;
 #pragma unroll
     for (int A = 0; A < (1 << KS); ++A)
         if ((A & ~Y) == 0) s += f[A];
@@ -78,14 +80,14 @@ __device__ __forceinline__ double corner(const double (&f)[1 << KS], int Y)
 }
 
 // q = a / b
-template <int KS>
-__device__ __forceinline__ void div(const double (&a)[1 << KS], const double (&b)[1 << KS],
-                                    double (&q)[1 << KS])
+template <int KS, typename T>
+__device__ __forceinline__ void div(const T (&a)[1 << KS], const T (&b)[1 << KS],
+                                    T (&q)[1 << KS])
 {
     constexpr int N = 1 << KS;
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) {
-        double s = a[Y];
+        T s = a[Y];
 #pragma unroll
         for (int A = 0; A < N; ++A) {
             if ((A & ~Y) != 0) continue;
@@ -97,27 +99,27 @@ __device__ __forceinline__ void div(const double (&a)[1 << KS], const double (&b
                 s = fma(-b[A], q[R | C], s);
             }
         }
-        q[Y] = s * rcp(corner<KS>(b, Y));
+        q[Y] = s * rcp(corner<KS, T>(b, Y));
     }
 }
 
 // r = log(1 + x)
-template <int KS>
+template <int KS, typename T>
 struct Log1p {
-    static __device__ __forceinline__ void run(const double (&x)[1 << KS], double (&r)[1 << KS])
+    static __device__ __forceinline__ void run(const T (&x)[1 << KS], T (&r)[1 << KS])
     {
         constexpr int H = 1 << (KS - 1);
-        double x0[H], x1[H], d[H], y[H], r0[H], r1[H];
+        T x0[H], x1[H], d[H], y[H], r0[H], r1[H];
 #pragma unroll
         for (int W = 0; W < H; ++W) {
             x0[W] = x[W];
             x1[W] = x[W + H];
             d[W] = x[W];
         }
-        d[0] += 1.0;
-        Log1p<KS - 1>::run(x0, r0);
-        div<KS - 1>(x1, d, y);
-        Log1p<KS - 1>::run(y, r1);
+        d[0] += T(1);
+        Log1p<KS - 1, T>::run(x0, r0);
+        div<KS - 1, T>(x1, d, y);
+        Log1p<KS - 1, T>::run(y, r1);
 #pragma unroll
         for (int W = 0; W < H; ++W) {
             r[W] = r0[W];
@@ -126,42 +128,42 @@ struct Log1p {
     }
 };
 
-template <>
-struct Log1p<0> {
-    static __device__ __forceinline__ void run(const double (&x)[1], double (&r)[1])
+template <typename T>
+struct Log1p<0, T> {
+    static __device__ __forceinline__ void run(const T (&x)[1], T (&r)[1])
     {
         r[0] = log1p(x[0]);
     }
 };
 
 // r = log(f) for f with a positive value at every corner
-template <int KS>
-__device__ __forceinline__ void log(const double (&f)[1 << KS], double (&r)[1 << KS])
+template <int KS, typename T>
+__device__ __forceinline__ void log(const T (&f)[1 << KS], T (&r)[1 << KS])
 {
     constexpr int N = 1 << KS;
-    double x[N];
-    const double inv0 = rcp(f[0]);
-    x[0] = 0.0;
+    T x[N];
+    const T inv0 = rcp(f[0]);
+    x[0] = 0;
 #pragma unroll
     for (int Y = 1; Y < N; ++Y) x[Y] = f[Y] * inv0;
-    Log1p<KS>::run(x, r);
+    Log1p<KS, T>::run(x, r);
     r[0] = ::log(f[0]);
 }
 
 // r = f^e for an integer e (wave-uniform)
-template <int KS>
-__device__ __forceinline__ void powi(const double (&f)[1 << KS], int e, double (&r)[1 << KS])
+template <int KS, typename T>
+__device__ __forceinline__ void powi(const T (&f)[1 << KS], int e, T (&r)[1 << KS])
 {
     constexpr int N = 1 << KS;
-    double base[N], one[N];
+    T base[N], one[N];
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) {
-        one[Y] = Y == 0 ? 1.0 : 0.0;
+        one[Y] = Y == 0 ? T(1) : T(0);
         r[Y] = one[Y];
     }
     if (e == 0) return;
     if (e < 0) {
-        div<KS>(one, f, base);
+        div<KS, T>(one, f, base);
         e = -e;
     } else {
 #pragma unroll
@@ -170,31 +172,31 @@ __device__ __forceinline__ void powi(const double (&f)[1 << KS], int e, double (
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) r[Y] = base[Y];
     for (int k = 1; k < e; ++k) {
-        double tmp[N];
-        mul<KS>(r, base, tmp);
+        T tmp[N];
+        mul<KS, KS, T>(r, base, tmp);
 #pragma unroll
         for (int Y = 0; Y < N; ++Y) r[Y] = tmp[Y];
     }
 }
 
 // r = exp(x) - 1
-template <int KS>
+template <int KS, typename T>
 struct Expm1 {
-    static __device__ __forceinline__ void run(const double (&x)[1 << KS], double (&r)[1 << KS])
+    static __device__ __forceinline__ void run(const T (&x)[1 << KS], T (&r)[1 << KS])
     {
         constexpr int H = 1 << (KS - 1);
-        double x0[H], x1[H], r0[H], r1[H], e0[H], p[H];
+        T x0[H], x1[H], r0[H], r1[H], e0[H], p[H];
 #pragma unroll
         for (int W = 0; W < H; ++W) {
             x0[W] = x[W];
             x1[W] = x[W + H];
         }
-        Expm1<KS - 1>::run(x0, r0);
-        Expm1<KS - 1>::run(x1, r1);
+        Expm1<KS - 1, T>::run(x0, r0);
+        Expm1<KS - 1, T>::run(x1, r1);
 #pragma unroll
         for (int W = 0; W < H; ++W) e0[W] = r0[W];
-        e0[0] += 1.0;
-        mul<KS - 1>(e0, r1, p);
+        e0[0] += T(1);
+        mul<KS - 1, KS - 1, T>(e0, r1, p);
 #pragma unroll
         for (int W = 0; W < H; ++W) {
             r[W] = r0[W];
@@ -203,26 +205,26 @@ struct Expm1 {
     }
 };
 
-template <>
-struct Expm1<0> {
-    static __device__ __forceinline__ void run(const double (&x)[1], double (&r)[1])
+template <typename T>
+struct Expm1<0, T> {
+    static __device__ __forceinline__ void run(const T (&x)[1], T (&r)[1])
     {
         r[0] = expm1(x[0]);
     }
 };
 
 // r = exp(x)
-template <int KS>
-__device__ __forceinline__ void exp(const double (&x)[1 << KS], double (&r)[1 << KS])
+template <int KS, typename T>
+__device__ __forceinline__ void exp(const T (&x)[1 << KS], T (&r)[1 << KS])
 {
     constexpr int N = 1 << KS;
-    double y[N], e[N];
+    T y[N], e[N];
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) y[Y] = x[Y];
-    y[0] = 0.0;
-    Expm1<KS>::run(y, e);
-    const double s = ::exp(x[0]);
-    e[0] += 1.0;
+    y[0] = 0;
+    Expm1<KS, T>::run(y, e);
+    const T s = ::exp(x[0]);
+    e[0] += T(1);
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) r[Y] = s * e[Y];
 }

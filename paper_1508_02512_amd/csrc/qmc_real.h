@@ -1,0 +1,397 @@
+// Real (Euclidean) integrand kernel: shifted rank-1 lattice points generated
+// in registers (Section III, Eqs. 17-18), Korobov periodiser (Eq. 21 at
+// order r), sector integrand of Eq. 9 with the pole subtraction of Eq. 11
+// and its eps expansion, compensated per-shift sums.
+//
+// One work-group of 256 lanes (four wave64) processes one work item: a tile
+// of consecutive lattice indices of one (kinematic point, sector, shift).
+// Sector data are wave-uniform (scalar loads, SGPRs) and the term loops are
+// scalar loops; each lane owns one lattice point at a time and walks the
+// tile with stride 256 by incremental modular addition.
+//
+// T is the evaluation type: double (QMC_FP64) or float (QMC_FP32_EVAL).
+// Lattice points, the shift and the accumulation are FP64 in both.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qmc_common.h"
+#include "qmc_device.h"
+#include "qmc_mobius.h"
+
+namespace qmc_real {
+
+using namespace qmc;
+
+template <typename T>
+__device__ __forceinline__ T tmono(uint32_t e, const T *t, const T *t2, const T *t3)
+{
+    T v = 1;
+#pragma unroll
+    for (int j = 0; j < QMC_DMAX; ++j) {
+        const uint32_t ej = (e >> (4 * j)) & 15u;
+        if (ej == 0u) continue;
+        if (ej == 1u) {
+            v *= t[j];
+        } else if (ej == 2u) {
+            v *= t2[j];
+        } else if (ej == 3u) {
+            v *= t3[j];
+        } else {
+            T p = t2[j] * t2[j];
+            for (uint32_t k = 4u; k < ej; ++k) p *= t[j];
+            v *= p;
+        }
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T tpowi(T x, int e)
+{
+    T r = 1;
+    const int a = e < 0 ? -e : e;
+    for (int k = 0; k < a; ++k) r *= x;
+    return e < 0 ? mobius::rcp(r) : r;
+}
+
+template <typename T>
+__device__ __forceinline__ void tkorobov(int r, T y, T u, T &t, T &w)
+{
+    if (r == 2) {
+        t = y * y * y * fma(y, fma(T(6), y, T(-15)), T(10));
+        w = T(30) * (y * u) * (y * u);
+    } else if (r == 1) {
+        t = y * y * fma(T(-2), y, T(3));
+        w = T(6) * y * u;
+    } else if (r == 3) {
+        t = y * y * y * y * fma(y, fma(y, fma(T(-20), y, T(70)), T(-84)), T(35));
+        const T yu = y * u;
+        w = T(140) * yu * yu * yu;
+    } else {
+        t = y;
+        w = 1;
+    }
+}
+
+// Whether a sector with KS poles takes the Moebius-coefficient path
+// (cancellation-free) rather than corner values.
+template <typename T, int KS>
+constexpr bool use_mobius()
+{
+    return sizeof(T) == sizeof(float) ? KS >= 1 : KS >= 2;
+}
+
+template <int KS, int K, typename T>
+struct Point {
+    T SU[1 << KS];          // U, F coefficients per pole mask (Moebius coefficients)
+    T SF[1 << KS];
+    T E[KS > 0 ? KS : 1][K];   // (b_j ln t_j)^r / r! of the pole variables
+    T invt[KS > 0 ? KS : 1];
+    T lt[KS > 0 ? KS : 1];
+    T LN;                   // sum_{j >= ks} b_j ln t_j
+    int bad;                // U or F not positive at some corner
+};
+
+// ---- corner path (few poles) -------------------------------------------
+
+template <int KS, int K, typename T>
+__device__ __forceinline__ void leaf(const qmc_sec_dev *S, Point<KS, K, T> &P, int X, T (&h)[K])
+{
+    constexpr int full = (1 << KS) - 1;
+    const T u = P.SU[full ^ X];
+    const T f = P.SF[full ^ X];
+    P.bad |= !(u > T(0)) | !(f > T(0));
+    const T lu = log(u), lf = log(f);
+    T pre;
+    if (S->u0i != QMC_NO_INT && S->f0i != QMC_NO_INT)
+        pre = tpowi(u, S->u0i) * tpowi(f, S->f0i);
+    else
+        pre = exp(T(S->u0) * lu + T(S->f0) * lf);
+    const T L = fma(T(S->u1), lu, fma(T(S->f1), lf, P.LN));
+    h[0] = pre;
+#pragma unroll
+    for (int q = 1; q < K; ++q) h[q] = h[q - 1] * L * (T(1) / T(q));
+}
+
+// Fold one pole variable (Eq. 11 with alpha = -1):
+//   G_R <- G_{R+j}/(b_j eps) + t_j^{-1} t_j^{b_j eps} (G_R - G_{R+j}),
+// index q of the series staying order q - (folds done).
+template <int K, typename T>
+__device__ __forceinline__ void fold(T (&A)[K], const T (&B)[K], T invb, T invt, const T (&E)[K])
+{
+    T D[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) D[q] = A[q] - B[q];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        T s = 0;
+#pragma unroll
+        for (int r = 0; r < q; ++r) s = fma(E[r], D[q - 1 - r], s);
+        A[q] = fma(B[q], invb, invt * s);
+    }
+}
+
+template <int LEVEL, int XB, int KS, int K, typename T>
+struct Tree {
+    static __device__ __forceinline__ void run(const qmc_sec_dev *S, Point<KS, K, T> &P,
+                                               T (&out)[K])
+    {
+        T B[K];
+        Tree<LEVEL - 1, XB, KS, K, T>::run(S, P, out);
+        Tree<LEVEL - 1, XB | (1 << (LEVEL - 1)), KS, K, T>::run(S, P, B);
+        fold<K, T>(out, B, T(S->inv_b[LEVEL - 1]), P.invt[LEVEL - 1], P.E[LEVEL - 1]);
+    }
+};
+
+template <int XB, int KS, int K, typename T>
+struct Tree<0, XB, KS, K, T> {
+    static __device__ __forceinline__ void run(const qmc_sec_dev *S, Point<KS, K, T> &P,
+                                               T (&out)[K])
+    {
+        leaf<KS, K, T>(S, P, XB, out);
+    }
+};
+
+// ---- Moebius path -----------------------------------------------------------
+
+// g[q + r + |Y|] += CY[Y] LY[Y]^r / r! h_q^[Y] for each order q of h, with
+// h_{q+1} = h_q B / (q + 1) formed only on the subsets that still contribute.
+template <int KS, int K, int Q, typename T>
+struct Accum {
+    static __device__ __forceinline__ void run(const T (&B)[1 << KS], T (&H)[1 << KS],
+                                               const T (&CY)[1 << KS], const T (&LY)[1 << KS],
+                                               T (&g)[K])
+    {
+        constexpr int N = 1 << KS;
+#pragma unroll
+        for (int Y = 0; Y < N; ++Y) {
+            const int pc = __builtin_popcount(Y);
+            if (Q + pc >= K) continue;
+            T e = CY[Y] * H[Y];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const int o = Q + r + pc;
+                if (o < K) {
+                    g[o] += e;
+                    e *= LY[Y] * (T(1) / T(r + 1));
+                }
+            }
+        }
+        if constexpr (Q + 1 < K) {
+            constexpr int MAXPC = K - 2 - Q < KS ? K - 2 - Q : KS;
+            T nt[N];
+            mobius::mul<KS, MAXPC, T>(H, B, nt);
+#pragma unroll
+            for (int Y = 0; Y < N; ++Y)
+                H[Y] = __builtin_popcount(Y) <= MAXPC ? nt[Y] * (T(1) / T(Q + 1)) : T(0);
+            Accum<KS, K, Q + 1, T>::run(B, H, CY, LY, g);
+        }
+    }
+};
+
+// The subtracted integrand from Moebius coefficients (see qmc_mobius.h):
+// h = U^(u0+u1 eps) F^(f0+f1 eps) exp(eps LN) = Pre exp(eps B) with
+// B = u1 log U + f1 log F + LN, accumulated into
+//   g = sum_Y prod_{j not in Y} 1/(b_j eps) prod_{j in Y} t_j^-1 t_j^(b_j eps) h^[Y],
+// index o of g holding order o - KS.
+template <int KS, int K, typename T>
+__device__ __forceinline__ void mobius_series(const qmc_sec_dev *S, Point<KS, K, T> &P,
+                                              T (&g)[K])
+{
+    constexpr int N = 1 << KS;
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y)
+        P.bad |= !(mobius::corner<KS, T>(P.SU, Y) > T(0)) |
+                 !(mobius::corner<KS, T>(P.SF, Y) > T(0));
+    T lU[N], lF[N], B[N], H[N];
+    mobius::log<KS, T>(P.SU, lU);
+    mobius::log<KS, T>(P.SF, lF);
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y) B[Y] = fma(T(S->u1), lU[Y], T(S->f1) * lF[Y]);
+    B[0] += P.LN;
+    if (S->u0i != QMC_NO_INT && S->f0i != QMC_NO_INT) {
+        T pu[N], pf[N];
+        mobius::powi<KS, T>(P.SU, S->u0i, pu);
+        mobius::powi<KS, T>(P.SF, S->f0i, pf);
+        mobius::mul<KS, KS, T>(pu, pf, H);
+    } else {
+        T x[N];
+#pragma unroll
+        for (int Y = 0; Y < N; ++Y) x[Y] = fma(T(S->u0), lU[Y], T(S->f0) * lF[Y]);
+        mobius::exp<KS, T>(x, H);
+    }
+    T CY[N], LY[N];
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y) {
+        T c = 1, L = 0;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            if (Y >> j & 1) {
+                c *= P.invt[j];
+                L = fma(T(S->b[j]), P.lt[j], L);
+            } else {
+                c *= T(S->inv_b[j]);
+            }
+        }
+        CY[Y] = c;
+        LY[Y] = L;
+    }
+#pragma unroll
+    for (int o = 0; o < K; ++o) g[o] = 0;
+    Accum<KS, K, 0, T>::run(B, H, CY, LY, g);
+}
+
+// ---- kernel -------------------------------------------------------------
+
+template <int KS, int K, typename T>
+__global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
+{
+    const int item_id = A.item_begin + (int)blockIdx.x;
+    if (item_id >= A.item_end) return;
+    const qmc_item it = A.items[item_id];
+    const qmc_sec_dev *S = A.sec + it.sector;
+    const qmc_lat_dev *L = A.lat + it.lat;
+    const int d = S->dim;
+    const uint32_t n = L->n;
+    const double inv_n = L->inv_n;
+    const double *coef = A.tcoef + (size_t)it.point * A.n_terms;
+    const double *shift = A.shifts + it.shift * QMC_DMAX;
+    const int r = A.korobov_r;
+
+    uint32_t l[QMC_DMAX], step[QMC_DMAX];
+    double dl[QMC_DMAX];
+#pragma unroll
+    for (int j = 0; j < QMC_DMAX; ++j) {
+        l[j] = 0u;
+        step[j] = 0u;
+        dl[j] = 0.0;
+        if (j < d) {
+            const uint64_t z = L->z[j];
+            l[j] = (uint32_t)(((uint64_t)(it.start + it.stride * threadIdx.x) * z) % n);
+            step[j] = (uint32_t)(((uint64_t)QMC_BLOCK * it.stride * z) % n);
+            dl[j] = shift[S->perm[j]];
+        }
+    }
+
+    double acc[1][K], cmp[1][K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[0][q] = cmp[0][q] = 0.0;
+    int viol = 0;
+
+    const int np = (int)((it.count + QMC_BLOCK - 1) / QMC_BLOCK);
+    for (int p = 0; p < np; ++p) {
+        const uint32_t off = threadIdx.x + (uint32_t)p * QMC_BLOCK;
+        if (off < it.count) {
+            T t[QMC_DMAX], t2[QMC_DMAX], t3[QMC_DMAX], w = 1;
+            bool skip = false;
+#pragma unroll
+            for (int j = 0; j < QMC_DMAX; ++j) {
+                t[j] = 1;
+                if (j < d) {
+                    double y = fma((double)l[j], inv_n, dl[j]);
+                    if (y >= 1.0) y -= 1.0;
+                    T wj;
+                    tkorobov<T>(r, T(y), T(1.0 - y), t[j], wj);
+                    w *= wj;
+                    skip |= (t[j] == T(0));
+                }
+                t2[j] = t[j] * t[j];
+                t3[j] = t2[j] * t[j];
+            }
+            if (!(w == T(0) || skip)) {
+                Point<KS, K, T> P;
+                P.bad = 0;
+                // non-pole monomial prod_{j >= ks} t_j^(a_j + b_j eps)
+                T pn = 1, LN = 0;
+#pragma unroll
+                for (int j = 0; j < QMC_DMAX; ++j) {
+                    if (j < d) {
+                        constexpr int pole_lim = KS;
+                        const bool pole = j < pole_lim;
+                        const T bj = T(S->b[j]);
+                        if (pole || S->b[j] != 0.0 || S->aint[j] == QMC_NO_INT) {
+                            const T lt = log(t[j]);
+                            if (pole) {
+                                const int jp = pole ? j : 0;
+                                P.invt[jp] = mobius::rcp(t[j]);
+                                P.lt[jp] = lt;
+                                const T x = bj * lt;
+                                P.E[jp][0] = 1;
+#pragma unroll
+                                for (int q = 1; q < K; ++q)
+                                    P.E[jp][q] = P.E[jp][q - 1] * x * (T(1) / T(q));
+                            } else {
+                                LN = fma(bj, lt, LN);
+                                if (S->aint[j] == QMC_NO_INT) pn *= exp(T(S->a[j]) * lt);
+                            }
+                        }
+                        if (!pole && S->aint[j] != QMC_NO_INT)
+                            for (int k = 0; k < S->aint[j]; ++k) pn *= t[j];
+                    }
+                }
+                P.LN = LN;
+                // U and F: one pass over the terms grouped by pole mask
+#pragma unroll
+                for (int m = 0; m < (1 << KS); ++m) {
+                    T su = 0, sf = 0;
+                    for (int q = S->um[m]; q < S->um[m + 1]; ++q)
+                        su = fma(T(coef[q]), tmono<T>(A.texp[q], t, t2, t3), su);
+                    for (int q = S->fm[m]; q < S->fm[m + 1]; ++q)
+                        sf = fma(T(coef[q]), tmono<T>(A.texp[q], t, t2, t3), sf);
+                    P.SU[m] = su;
+                    P.SF[m] = sf;
+                }
+                T g[K];
+                if constexpr (use_mobius<T, KS>()) {
+                    mobius_series<KS, K, T>(S, P, g);
+                } else {
+                    // subset sums: the value at the corner where the poles in X are 0
+#pragma unroll
+                    for (int i = 0; i < KS; ++i)
+#pragma unroll
+                        for (int Y = 0; Y < (1 << KS); ++Y)
+                            if (Y >> i & 1) {
+                                P.SU[Y] += P.SU[Y ^ (1 << i)];
+                                P.SF[Y] += P.SF[Y ^ (1 << i)];
+                            }
+                    Tree<KS, 0, KS, K, T>::run(S, P, g);
+                }
+                if (P.bad) {
+                    viol += 1;
+                } else {
+                    const double wp = (double)(w * pn);
+#pragma unroll
+                    for (int q = 0; q < K; ++q) neumaier(acc[0][q], cmp[0][q], wp * (double)g[q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < QMC_DMAX; ++j) {
+            if (j < d) {
+                const uint32_t v = l[j] + step[j];
+                l[j] = v >= n ? v - n : v;
+            }
+        }
+    }
+
+    double *dst = A.partial + (size_t)item_id * A.kstride * 4;
+    block_reduce_store<K, 1>(acc, cmp, dst, A.kstride);
+    store_violations(viol, A.viol + item_id);
+}
+
+} // namespace qmc_real
+
+#define QMC_REAL_CASE(KS, KB, T)                                                    \
+    if (ks == KS && kb == KB) {                                                     \
+        hipLaunchKernelGGL((qmc_real::qmc_eval_real<KS, KS + KB, T>), dim3(grid),    \
+                           dim3(QMC_BLOCK), 0, stream, args);                       \
+        return hipGetLastError();                                                   \
+    }
+
+#define QMC_REAL_CASES(T)                                                           \
+    QMC_REAL_CASE(0, 1, T) QMC_REAL_CASE(0, 2, T) QMC_REAL_CASE(0, 3, T)           \
+    QMC_REAL_CASE(1, 1, T) QMC_REAL_CASE(1, 2, T) QMC_REAL_CASE(1, 3, T)           \
+    QMC_REAL_CASE(2, 1, T) QMC_REAL_CASE(2, 2, T) QMC_REAL_CASE(2, 3, T)           \
+    QMC_REAL_CASE(3, 1, T) QMC_REAL_CASE(3, 2, T) QMC_REAL_CASE(3, 3, T)           \
+    QMC_REAL_CASE(4, 1, T) QMC_REAL_CASE(4, 2, T) QMC_REAL_CASE(4, 3, T)

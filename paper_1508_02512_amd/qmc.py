@@ -67,7 +67,8 @@ class qmc_result(C.Structure):
     _fields_ = [("coeff", P(qmc_coeff)), ("per_shift", P(C.c_double)),
                 ("sector_sums", P(C.c_double)), ("evals", C.c_uint64), ("n_final", C.c_uint64),
                 ("status", C.c_int32), ("deform_violations", C.c_int32),
-                ("kernel_ms", C.c_double), ("algo_flops", C.c_double)]
+                ("kernel_ms", C.c_double), ("algo_flops", C.c_double),
+                ("latency_ms", C.c_double), ("steps", C.c_int32), ("reserved", C.c_int32)]
 
 
 class qmc_request(C.Structure):
@@ -98,6 +99,7 @@ _SIGS = {
     "qmc_poll": (C.c_int, [C.c_void_p, C.c_uint64, P(qmc_result)]),
     "qmc_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double, P(qmc_result)]),
     "qmc_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "qmc_release": (C.c_int, [C.c_void_p, C.c_uint64]),
 }
 
 _lib = None
@@ -292,6 +294,55 @@ class Plan:
 
     def bind(self, kin, lattice, shifts, lat_per_sector=None):
         return Job(self, kin, lattice, shifts, lat_per_sector)
+
+
+class Request:
+    """Handle of one served request (continuous batching, see qmc.h)."""
+
+    def __init__(self, plan, ticket):
+        self.plan, self.ticket = plan, ticket
+
+    def _result(self):
+        res, coeff, _, _ = self.plan._result(1, 2, False, False)
+        return res, coeff
+
+    def wait(self, timeout=-1.0):
+        res, coeff = self._result()
+        rc = lib().qmc_wait(self.plan.ctx.h, self.ticket, float(timeout), C.byref(res))
+        if rc == QMC_PENDING:
+            return None
+        out = self.plan._pack(res, coeff, None, None, 1)
+        out["rc"] = rc
+        out["latency_ms"] = res.latency_ms
+        out["steps"] = res.steps
+        out["n_final"] = res.n_final
+        return out
+
+    def poll(self):
+        res, coeff = self._result()
+        rc = lib().qmc_poll(self.plan.ctx.h, self.ticket, C.byref(res))
+        if rc == QMC_PENDING:
+            return None
+        out = self.plan._pack(res, coeff, None, None, 1)
+        out.update(rc=rc, latency_ms=res.latency_ms, steps=res.steps, n_final=res.n_final)
+        return out
+
+    def cancel(self):
+        self.plan.ctx.check(lib().qmc_cancel(self.plan.ctx.h, self.ticket))
+
+    def release(self):
+        lib().qmc_release(self.plan.ctx.h, self.ticket)
+
+
+def submit(plan, kin, target, n0, n_max, m, seed, z):
+    """Queue one request of `plan` at kinematic vector `kin`."""
+    kin = np.ascontiguousarray(kin, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.uint32)
+    req = qmc_request(_dptr(kin), float(target), int(n0), int(n_max), int(m), int(seed),
+                      z.ctypes.data_as(P(C.c_uint32)))
+    t = C.c_uint64()
+    plan.ctx.check(lib().qmc_submit(plan.ctx.h, plan.h, C.byref(req), C.byref(t)))
+    return Request(plan, t.value)
 
 
 class Job:

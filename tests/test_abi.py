@@ -36,4 +36,4 @@ def test_binding_structs_match_header_sizes():
     assert ctypes.sizeof(qmc.qmc_sector) == 8 + 16 + 48 + 32 + 16
     assert ctypes.sizeof(qmc.qmc_lattice) == 16
     assert ctypes.sizeof(qmc.qmc_coeff) == 32
-    assert ctypes.sizeof(qmc.qmc_result) == 24 + 16 + 8 + 16
+    assert ctypes.sizeof(qmc.qmc_result) == 24 + 16 + 8 + 16 + 16

@@ -31,12 +31,12 @@ def test_massless_bubble_negative_constant_f():
 
 
 def test_box_physical():
-    print("box s=3 t=-2 lambda=0.3", flush=True)
-    res, _ = compare_sectors("box", {"s": 3.0, "t": -2.0}, 10007, 4, lam=0.3)
+    print("box s=3 t=-2 lambda=0.5", flush=True)
+    res, _ = compare_sectors("box", {"s": 3.0, "t": -2.0}, 10007, 4, lam=0.5)
     assert res["violations"] == 0
 
 
-@pytest.mark.parametrize("lam", [0.05, 0.1])
+@pytest.mark.parametrize("lam", [0.25, 0.5])
 def test_np_vertex_physical(lam):
     print(f"np_vertex s=4.5 lambda={lam}", flush=True)
     res, _ = compare_sectors("np_vertex", {"s": 4.5, "msq": 1.0}, 1009, 2, lam=lam)
@@ -44,8 +44,8 @@ def test_np_vertex_physical(lam):
 
 
 def test_np_vertex_lambda_independence():
-    plan1, info = gpu_plan("np_vertex", lam=0.05)
-    plan2, _ = gpu_plan("np_vertex", lam=0.1)
+    plan1, info = gpu_plan("np_vertex", lam=0.25)
+    plan2, _ = gpu_plan("np_vertex", lam=0.5)
     args = (fe.kin_vector(info, {"s": 4.5, "msq": 1.0}), (262139, lattice(262139)),
             shift_table(0, 8, 8))
     a, b = plan1.integrate(*args), plan2.integrate(*args)
@@ -56,13 +56,13 @@ def test_np_vertex_lambda_independence():
 
 
 def test_np_vertex_lambda_too_large_is_reported():
-    """lambda = 0.5 pushes Im F(z) above 0 at some points for this integral;
-    the kernel counts them and the call returns QMC_EDEFORM (the oracle
-    counts violations on the same inputs too)."""
+    """lambda = 1 (in units of the largest |coefficient| of F) pushes Im F(z)
+    above 0 at some points for this integral; the kernel counts them and the
+    call returns QMC_EDEFORM (the oracle counts violations too)."""
     from oracle import qmc as oq
     from oracle.decompose import decompose as odec
     from seeded_inputs.problems import PROBLEMS
-    plan, info = gpu_plan("np_vertex", lam=0.5)
+    plan, info = gpu_plan("np_vertex", lam=1.0)
     kin = {"s": 4.5, "msq": 1.0}
     res = plan.integrate(fe.kin_vector(info, kin), (1009, lattice(1009)), shift_table(0, 2, 8),
                          allow_violations=True)
@@ -70,8 +70,9 @@ def test_np_vertex_lambda_too_large_is_reported():
     osecs, oinfo = odec(PROBLEMS["np_vertex"])
     bad = 0
     for s in osecs:
-        _, _, c = oq.sector_sums(oq.NumericSector(s, oinfo, kin), 1009, lattice(1009),
-                                 shift_table(0, 2, 8), 2, 0.5, 0, 1)
+        ns = oq.NumericSector(s, oinfo, kin)
+        _, _, c = oq.sector_sums(ns, 1009, lattice(1009), shift_table(0, 2, 8), 2,
+                                 oq.effective_lambda(ns, 1.0), 0, 1)
         bad += int(c[:, :2].sum())
     assert bad > 0
     plan.close()
@@ -81,5 +82,5 @@ def test_np_vertex_lambda_too_large_is_reported():
 def test_triangle2l(s):
     """Below threshold the sectors run undeformed (all F coefficients >= 0)."""
     print(f"triangle2l s={s}", flush=True)
-    res, _ = compare_sectors("triangle2l", {"s": s, "msq": 1.0}, 1009, 2, lam=0.1)
+    res, _ = compare_sectors("triangle2l", {"s": s, "msq": 1.0}, 1009, 2, lam=0.5)
     assert res["violations"] == 0

@@ -1,0 +1,96 @@
+"""Serving: continuous batching with embedded-lattice doubling."""
+
+import numpy as np
+import pytest
+
+from gpu_util import ctx, gpu_plan
+from paper_1508_02512_amd import frontend as fe
+from paper_1508_02512_amd import qmc
+from seeded_inputs.lattice import lattice
+from seeded_inputs.rng import shift_table
+
+pytestmark = pytest.mark.gpu
+
+Z = lattice(1 << 24)          # odd Korobov vector, used for every n = 2^k
+
+
+def _box_kin(info, s=-3.0, t=-2.0):
+    return fe.kin_vector(info, {"s": s, "t": t})
+
+
+def test_single_request_converges_and_matches_integrate():
+    print("serve: one box request", flush=True)
+    plan, info = gpu_plan("box")
+    kin = _box_kin(info)
+    r = qmc.submit(plan, kin, 1e-6, 1 << 12, 1 << 22, 8, 7, Z).wait(120)
+    assert r["rc"] == 0 and r["steps"] >= 2
+    # the doubled lattice reproduces one pass over the same 2^k points
+    ref = plan.integrate(kin, (r["n_final"], Z), shift_table(7, 8, 8))
+    assert np.allclose(r["mean"], ref["mean"], rtol=1e-12, atol=1e-14)
+    assert np.allclose(r["err_re"], ref["err_re"], rtol=1e-8, atol=1e-16)
+    want = np.array([0.666666666666667, -0.982063599677040, -1.48360889993076])
+    assert np.all(np.abs(r["mean"][0].real - want) <= 6 * r["err_re"][0] + 1e-12)
+    plan.close()
+
+
+def test_same_result_alone_and_in_mix():
+    print("serve: alone vs mix", flush=True)
+    box, binfo = gpu_plan("box")
+    bub, uinfo = gpu_plan("bubble_massive", lam=0.5)
+    np_, ninfo = gpu_plan("np_vertex", lam=0.5)
+    kin = _box_kin(binfo, -2.5, -1.5)
+    alone = qmc.submit(box, kin, 1e-5, 1 << 12, 1 << 20, 8, 11, Z).wait(120)
+    others = []
+    rng = np.random.default_rng(0)
+    for i in range(12):
+        if i % 3 == 0:
+            k = fe.kin_vector(uinfo, {"s": float(rng.uniform(4.2, 8.0)), "msq": 1.0})
+            others.append(qmc.submit(bub, k, 1e-4, 1 << 10, 1 << 20, 8, 100 + i, Z))
+        elif i % 3 == 1:
+            k = fe.kin_vector(ninfo, {"s": float(rng.uniform(4.2, 6.0)), "msq": 1.0})
+            others.append(qmc.submit(np_, k, 3e-3, 1 << 12, 1 << 18, 8, 100 + i, Z))
+        else:
+            k = _box_kin(binfo, float(rng.uniform(-5, -1)), float(rng.uniform(-5, -1)))
+            others.append(qmc.submit(box, k, 1e-4, 1 << 10, 1 << 20, 8, 100 + i, Z))
+    mixed = qmc.submit(box, kin, 1e-5, 1 << 12, 1 << 20, 8, 11, Z)
+    res = [o.wait(300) for o in others]
+    again = mixed.wait(300)
+    assert all(x is not None and x["rc"] in (0, -7) for x in res)
+    assert again["rc"] == 0 and alone["rc"] == 0
+    assert np.array_equal(alone["mean"], again["mean"])
+    assert np.array_equal(alone["err_re"], again["err_re"])
+    for p in (box, bub, np_):
+        p.close()
+
+
+def test_not_converged_and_cancel():
+    print("serve: n_max and cancel", flush=True)
+    plan, info = gpu_plan("box")
+    kin = _box_kin(info)
+    r = qmc.submit(plan, kin, 1e-14, 1 << 10, 1 << 12, 4, 1, Z).wait(60)
+    assert r["rc"] == -7 and r["n_final"] == 1 << 12
+    slow = qmc.submit(plan, kin, 1e-15, 1 << 20, 1 << 30, 4, 2, Z)
+    slow.cancel()
+    assert slow.wait(60)["rc"] == -9
+    plan.close()
+
+
+def test_budget_too_small():
+    print("serve: budget", flush=True)
+    small = qmc.Context(0, hbm_budget=8 << 20)
+    secs, info = fe.decompose(__import__("seeded_inputs.problems", fromlist=["x"]).PROBLEMS["doublebox"])
+    plan = small.plan(fe.sector_arrays(secs, info), info, 0, fe.prefactor_series(info, 12))
+    r = qmc.submit(plan, fe.kin_vector(info, {"s": -3.0, "t": -1.0}), 1e-3, 1 << 16, 1 << 20,
+                   16, 1, Z).wait(60)
+    assert r["rc"] == -5
+    plan.close()
+    small.close()
+
+
+def test_deformation_violation_reported():
+    print("serve: lambda too large", flush=True)
+    plan, info = gpu_plan("np_vertex", lam=1.0)
+    r = qmc.submit(plan, fe.kin_vector(info, {"s": 4.5, "msq": 1.0}), 1e-3, 1 << 10, 1 << 16,
+                   4, 1, Z).wait(60)
+    assert r["rc"] == -6 and r["violations"] > 0
+    plan.close()
