@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-time-to-target", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device copy (calibrates HBM counters)")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -154,6 +156,12 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     stream = torch.cuda.current_stream().cuda_stream
+    if args.copy_probe:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     kin_vals = {"s": -3.0, "t": -1.0}
     secs, info = fe.decompose(PROBLEMS["doublebox"])
     arrs = fe.sector_arrays(secs, info)

@@ -180,6 +180,31 @@ int qmc_run(qmc_job *job);
 int qmc_fetch(qmc_job *job, qmc_result *out);
 void qmc_job_free(qmc_job *job);
 
+/* ---- batching: graph replay and autotuning ---------------------------------
+ * qmc_job_set_graph: when enabled, the next qmc_run captures the job's whole
+ * launch sequence (integrand kernels of every class, the reduction, the copy
+ * of the group sums) into one HIP graph and later runs replay it.  The
+ * timing in qmc_result.kernel_ms then covers the whole graph.
+ *
+ * qmc_autotune: times candidate launch shapes on the given inputs (which
+ * should have the lattice sizes of the production runs; two shifts are
+ * enough) and remembers, per (plan, poles, kernel width, lattice-size
+ * octave), the fastest points-per-lane and persistent-grid setting.  Later
+ * binds with points_per_lane = 0 use them.  choices (may be NULL) receives
+ * up to max_choices entries; *n_choices is set to the number of classes. */
+typedef struct {
+    int32_t poles, width;        /* kernel class: poles, complex width (0 = real) */
+    int32_t points_per_lane;     /* chosen tile: 256 * points_per_lane indices per item */
+    int32_t grid_per_cu;         /* 0: one work-group per item; else persistent */
+    double ms;                   /* measured time of the class with that shape */
+} qmc_tune_choice;
+
+int qmc_job_set_graph(qmc_job *job, int enable);
+int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
+                 const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
+                 const double *shifts, int32_t m, qmc_tune_choice *choices,
+                 int32_t max_choices, int32_t *n_choices);
+
 /* ---- serving (continuous batching) ---------------------------------------
  * A request is one integral (a plan) at one kinematic point with a relative
  * error target.  A scheduler thread owned by the context admits requests

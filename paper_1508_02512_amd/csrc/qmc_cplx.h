@@ -297,11 +297,10 @@ __device__ __forceinline__ void corners_folded(const qmc_sec_dev *S, CplxPoint<D
     }
 }
 
+// One work item (a tile of one (point, sector, shift) group).
 template <int DM, int KS, int K>
-__global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
+__device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, const int item_id)
 {
-    const int item_id = A.item_begin + (int)blockIdx.x;
-    if (item_id >= A.item_end) return;
     const qmc_item it = A.items[item_id];
     const qmc_sec_dev *S = A.sec + it.sector;
     const qmc_lat_dev *L = A.lat + it.lat;
@@ -407,6 +406,19 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
     double *dst = A.partial + (size_t)item_id * A.kstride * 4;
     block_reduce_store<K, 2>(acc, cmp, dst, A.kstride);
     store_violations(viol, A.viol + item_id);
+}
+
+// Work-groups take items item_begin + blockIdx.x, + gridDim.x, ...: one item
+// per work-group when the grid covers the list, a persistent loop when the
+// grid is smaller.  Each item writes only its own slot, so the result does
+// not depend on the grid.
+template <int DM, int KS, int K>
+__global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
+{
+    for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
+        qmc_eval_cplx_item<DM, KS, K>(A, item);
+        __syncthreads();
+    }
 }
 
 } // namespace qmc_cplx

@@ -60,6 +60,7 @@ struct qmc_launch_args {
     const qmc_sec_dev *sec;
     const qmc_lat_dev *lat;  // [n_sectors]
     const uint32_t *texp;    // [n_terms] packed exponents of U and F terms
+    const double *texpd;     // [n_terms][QMC_DMAX] the same exponents as doubles
     const double *tcoef;     // [n_points][n_terms] coefficients at each point
     const uint32_t *dexp;    // [n_dterms] packed exponents of derivative terms
     const double *dcoef;     // [n_points][n_dterms]

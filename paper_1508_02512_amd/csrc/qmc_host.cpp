@@ -105,6 +105,9 @@ extern "C" int qmc_create(int device, size_t hbm_budget, int max_slots, qmc_ctx 
         return QMC_EDEVICE;
     }
     ctx->stream = ctx->own_stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->n_cu = prop.multiProcessorCount;
     *out = ctx;
     return QMC_OK;
 }
@@ -412,6 +415,12 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_texp, sizeof(uint32_t) * plan->texp.size());
     if (rc == QMC_OK && !plan->dexp.empty())
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
+    std::vector<double> texpd(plan->texp.size() * QMC_DMAX);
+    for (size_t t = 0; t < plan->texp.size(); ++t)
+        for (int j = 0; j < QMC_DMAX; ++j)
+            texpd[t * QMC_DMAX + j] = (double)((plan->texp[t] >> (4 * j)) & 15u);
+    if (rc == QMC_OK)
+        rc = qmc_dev_alloc(ctx, (void **)&plan->d_texpd, sizeof(double) * texpd.size());
     if (rc != QMC_OK) {
         qmc_plan_free(plan);
         return rc;
@@ -423,6 +432,9 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                       hipMemcpyHostToDevice);
     if (e == hipSuccess && !plan->dexp.empty())
         e = hipMemcpy(plan->d_dexp, plan->dexp.data(), sizeof(uint32_t) * plan->dexp.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(plan->d_texpd, texpd.data(), sizeof(double) * texpd.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         qmc_plan_free(plan);
@@ -468,6 +480,7 @@ extern "C" void qmc_plan_free(qmc_plan *plan)
     qmc_ctx *ctx = plan->ctx;
     qmc_dev_free(ctx, plan->d_sec, sizeof(qmc_sec_dev) * plan->secs.size());
     qmc_dev_free(ctx, plan->d_texp, sizeof(uint32_t) * plan->texp.size());
+    qmc_dev_free(ctx, plan->d_texpd, sizeof(double) * plan->texp.size() * QMC_DMAX);
     qmc_dev_free(ctx, plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
     delete plan;
 }
@@ -532,9 +545,9 @@ int qmc_sector_mode(const qmc_plan *plan, int s, const double *coef, double *lam
 hipError_t qmc_launch_class(const qmc_plan *plan, const qmc_class &c, const qmc_launch_args &A,
                             hipStream_t stream)
 {
-    if (c.deform) return qmc_launch_cplx(c.dm, c.ks, c.kb, A, c.end - c.begin, stream);
-    return qmc_launch_real(c.ks, c.kb, plan->opts.precision == QMC_FP32_EVAL, A, c.end - c.begin,
-                           stream);
+    const int grid = c.grid > 0 ? std::min(c.grid, c.end - c.begin) : c.end - c.begin;
+    if (c.deform) return qmc_launch_cplx(c.dm, c.ks, c.kb, A, grid, stream);
+    return qmc_launch_real(c.ks, c.kb, plan->opts.precision == QMC_FP32_EVAL, A, grid, stream);
 }
 
 void qmc_job_release(qmc_job *job)
@@ -546,6 +559,24 @@ void qmc_job_release(qmc_job *job)
     if (job->ev0) (void)hipEventDestroy(job->ev0);
     if (job->ev1) (void)hipEventDestroy(job->ev1);
     job->ev0 = job->ev1 = nullptr;
+    for (hipEvent_t e : job->ev_cls) (void)hipEventDestroy(e);
+    job->ev_cls.clear();
+    if (job->graph) (void)hipGraphExecDestroy(job->graph);
+    job->graph = nullptr;
+    if (job->h_out) (void)hipHostFree(job->h_out);
+    if (job->h_gviol) (void)hipHostFree(job->h_gviol);
+    job->h_out = nullptr;
+    job->h_gviol = nullptr;
+}
+
+std::string qmc_tune_key(const qmc_plan *plan, int ks, int dm, uint64_t n)
+{
+    int lg = 0;
+    while ((2ull << lg) <= n) ++lg;
+    char buf[128];
+    snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d", (const void *)plan, ks, dm,
+             plan->opts.precision, lg);
+    return buf;
 }
 
 template <class T>
@@ -566,7 +597,8 @@ static int job_upload(qmc_job *job, T **dptr, const T *src, size_t count)
 
 int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
                   const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
-                  const double *shifts, int32_t m, int ppl_override, qmc_job **out)
+                  const double *shifts, int32_t m, int ppl_override, int grid_override,
+                  bool class_timing, qmc_job **out)
 {
     if (!ctx || !plan || !kin || !shifts || !out) return set_err(ctx, QMC_EINVAL, "null argument");
     *out = nullptr;
@@ -621,7 +653,8 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
         ppl = (int)std::min<uint64_t>(std::max<uint64_t>(want, 4), 1 << 14);
     }
     job->ppl = ppl;
-    const uint64_t tile = (uint64_t)QMC_BLOCK * ppl;
+    uint64_t nmax_sec = 0;
+    for (int s = 0; s < ns; ++s) nmax_sec = std::max<uint64_t>(nmax_sec, job->n_per_sector[s]);
     const int n_groups = n_points * ns * m;
     std::vector<int32_t> gbeg(n_groups), gend(n_groups);
     std::vector<qmc_item> items;
@@ -650,6 +683,17 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
         c.deform = c.dm != 0;
         c.kb = plan->kb;
         c.begin = (int)items.size();
+        c.ppl = ppl;
+        c.grid = grid_override > 0 ? grid_override * ctx->n_cu : 0;
+        if (ppl_override <= 0 && plan->opts.points_per_lane <= 0) {
+            std::lock_guard<std::mutex> g(ctx->tune_mu);
+            auto t = ctx->tuned.find(qmc_tune_key(plan, c.ks, c.dm, nmax_sec));
+            if (t != ctx->tuned.end()) {
+                c.ppl = t->second.ppl;
+                c.grid = t->second.grid_per_cu * ctx->n_cu;
+            }
+        }
+        const uint64_t tile = (uint64_t)QMC_BLOCK * c.ppl;
         for (int p = 0; p < n_points; ++p)
             for (int s = 0; s < ns; ++s) {
                 if (key_of[(size_t)p * ns + s] != ki) continue;
@@ -705,8 +749,17 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
         delete job;
         return rc;
     }
-    job->h_out.resize((size_t)n_groups * plan->kstride * 2);
-    job->h_gviol.resize(n_groups);
+    job->h_out_n = (size_t)n_groups * plan->kstride * 2;
+    if (hipHostMalloc((void **)&job->h_out, sizeof(double) * job->h_out_n) != hipSuccess ||
+        hipHostMalloc((void **)&job->h_gviol, sizeof(int32_t) * n_groups) != hipSuccess) {
+        qmc_job_release(job);
+        delete job;
+        return set_err(ctx, QMC_ENOMEM, "pinned host allocation");
+    }
+    if (class_timing) {
+        job->ev_cls.resize(job->classes.size() + 1);
+        for (auto &e : job->ev_cls) (void)hipEventCreate(&e);
+    }
     *out = job;
     return QMC_OK;
 }
@@ -716,7 +769,8 @@ extern "C" int qmc_bind(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
                         const qmc_lattice *lat_per_sector, const double *shifts, int32_t m,
                         qmc_job **out)
 {
-    return qmc_bind_impl(ctx, plan, kin, n_points, lat, lat_per_sector, shifts, m, 0, out);
+    return qmc_bind_impl(ctx, plan, kin, n_points, lat, lat_per_sector, shifts, m, 0, 0, false,
+                         out);
 }
 
 extern "C" int qmc_run(qmc_job *job)
@@ -729,6 +783,7 @@ extern "C" int qmc_run(qmc_job *job)
     A.sec = plan->d_sec;
     A.lat = job->d_lat;
     A.texp = plan->d_texp;
+    A.texpd = plan->d_texpd;
     A.tcoef = job->d_coef;
     A.dexp = plan->d_dexp;
     A.dcoef = job->d_dcoef;
@@ -742,22 +797,51 @@ extern "C" int qmc_run(qmc_job *job)
     A.n_dterms = (int32_t)plan->dexp.size();
     A.kstride = plan->kstride;
     A.korobov_r = plan->opts.korobov_r;
-    HIP_CHECK(ctx, hipEventRecord(job->ev0, ctx->stream));
-    for (const qmc_class &c : job->classes) {
-        A.item_begin = c.begin;
-        A.item_end = c.end;
-        HIP_CHECK(ctx, qmc_launch_class(plan, c, A, ctx->stream));
+    auto enqueue = [&](bool timing) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; i < job->classes.size() && e == hipSuccess; ++i) {
+            const qmc_class &c = job->classes[i];
+            if (timing && !job->ev_cls.empty()) e = hipEventRecord(job->ev_cls[i], ctx->stream);
+            A.item_begin = c.begin;
+            A.item_end = c.end;
+            if (e == hipSuccess) e = qmc_launch_class(plan, c, A, ctx->stream);
+        }
+        if (e == hipSuccess && timing && !job->ev_cls.empty())
+            e = hipEventRecord(job->ev_cls.back(), ctx->stream);
+        if (e == hipSuccess && timing) e = hipEventRecord(job->ev1, ctx->stream);
+        if (e == hipSuccess)
+            e = qmc_launch_reduce(job->d_partial, job->d_viol, job->d_gbeg, job->d_gend,
+                                  job->n_groups, plan->kstride, job->d_out, job->d_gviol,
+                                  ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(job->h_out, job->d_out, sizeof(double) * job->h_out_n,
+                               hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(job->h_gviol, job->d_gviol, sizeof(int32_t) * job->n_groups,
+                               hipMemcpyDeviceToHost, ctx->stream);
+        return e;
+    };
+    if (job->use_graph) {
+        // the whole sequence as one graph, captured once and replayed
+        if (!job->graph) {
+            hipGraph_t g = nullptr;
+            HIP_CHECK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            const hipError_t e = enqueue(false);
+            const hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
+            HIP_CHECK(ctx, e);
+            HIP_CHECK(ctx, e2);
+            const hipError_t e3 = hipGraphInstantiate(&job->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_CHECK(ctx, e3);
+        }
+        HIP_CHECK(ctx, hipEventRecord(job->ev0, ctx->stream));
+        HIP_CHECK(ctx, hipGraphLaunch(job->graph, ctx->stream));
+        HIP_CHECK(ctx, hipEventRecord(job->ev1, ctx->stream));
+    } else {
+        // ev0 .. ev1 brackets the integrand kernels only
+        HIP_CHECK(ctx, hipEventRecord(job->ev0, ctx->stream));
+        HIP_CHECK(ctx, enqueue(true));
     }
-    HIP_CHECK(ctx, hipEventRecord(job->ev1, ctx->stream));
-    HIP_CHECK(ctx, qmc_launch_reduce(job->d_partial, job->d_viol, job->d_gbeg, job->d_gend,
-                                     job->n_groups, plan->kstride, job->d_out, job->d_gviol,
-                                     ctx->stream));
-    HIP_CHECK(ctx, hipMemcpyAsync(job->h_out.data(), job->d_out,
-                                  sizeof(double) * job->h_out.size(), hipMemcpyDeviceToHost,
-                                  ctx->stream));
-    HIP_CHECK(ctx, hipMemcpyAsync(job->h_gviol.data(), job->d_gviol,
-                                  sizeof(int32_t) * job->h_gviol.size(), hipMemcpyDeviceToHost,
-                                  ctx->stream));
     job->launched = true;
     return QMC_OK;
 }
@@ -850,9 +934,9 @@ extern "C" int qmc_fetch(qmc_job *job, qmc_result *out)
     float ms = 0.0f;
     HIP_CHECK(ctx, hipEventElapsedTime(&ms, job->ev0, job->ev1));
     job->launched = false;
-    qmc_assemble(job->plan, job->n_points, job->m, job->n_per_sector, job->h_out.data(), out);
+    qmc_assemble(job->plan, job->n_points, job->m, job->n_per_sector, job->h_out, out);
     long viol = 0;
-    for (int32_t v : job->h_gviol) viol += v;
+    for (int i = 0; i < job->n_groups; ++i) viol += job->h_gviol[i];
     out->evals = job->evals;
     out->n_final = job->n_per_sector.empty() ? 0 : job->n_per_sector[0];
     out->deform_violations = (int32_t)std::min<long>(viol, INT32_MAX);
@@ -887,4 +971,87 @@ extern "C" int qmc_integrate(qmc_ctx *ctx, const qmc_plan *plan, const double *k
     if (!rc) rc = qmc_fetch(job, out);
     qmc_job_free(job);
     return rc;
+}
+
+extern "C" int qmc_job_set_graph(qmc_job *job, int enable)
+{
+    if (!job) return QMC_EINVAL;
+    if (job->launched) return set_err(job->ctx, QMC_EINVAL, "job is running");
+    job->use_graph = enable != 0;
+    if (!job->use_graph && job->graph) {
+        (void)hipGraphExecDestroy(job->graph);
+        job->graph = nullptr;
+    }
+    return QMC_OK;
+}
+
+// Candidate launch shapes, timed per kernel class on the caller's inputs.
+extern "C" int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
+                            int32_t n_points, const qmc_lattice *lat,
+                            const qmc_lattice *lat_per_sector, const double *shifts, int32_t m,
+                            qmc_tune_choice *choices, int32_t max_choices, int32_t *n_choices)
+{
+    if (!ctx || !plan) return QMC_EINVAL;
+    static const int ppls[] = {4, 16, 64, 256, 1024};
+    static const int grids[] = {0, 4, 8};
+    std::map<std::string, std::pair<qmc_tune, std::pair<int, int>>> best;
+    for (int ppl : ppls) {
+        qmc_job *job = nullptr;
+        int rc = qmc_bind_impl(ctx, plan, kin, n_points, lat, lat_per_sector, shifts, m, ppl, 0,
+                               true, &job);
+        if (rc) return rc;
+        uint64_t nmax = 0;
+        for (uint64_t v : job->n_per_sector) nmax = std::max(nmax, v);
+        bool warmed = false;
+        for (int gpc : grids) {
+            for (qmc_class &c : job->classes) c.grid = gpc * ctx->n_cu;
+            for (int rep = warmed ? 0 : -1; rep < 1; ++rep) {
+                rc = qmc_run(job);
+                if (!rc) {
+                    const hipError_t e = hipStreamSynchronize(ctx->stream);
+                    if (e != hipSuccess) rc = set_err(ctx, QMC_EDEVICE, "autotune: %s",
+                                                      hipGetErrorString(e));
+                }
+                job->launched = false;
+                if (rc) break;
+            }
+            warmed = true;
+            if (rc) break;
+            for (size_t i = 0; i < job->classes.size(); ++i) {
+                const qmc_class &c = job->classes[i];
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, job->ev_cls[i], job->ev_cls[i + 1]) != hipSuccess)
+                    continue;
+                const std::string key = qmc_tune_key(plan, c.ks, c.dm, nmax);
+                auto it = best.find(key);
+                if (it == best.end() || ms < it->second.first.ms) {
+                    qmc_tune t;
+                    t.ppl = ppl;
+                    t.grid_per_cu = gpc;
+                    t.ms = ms;
+                    best[key] = {t, {c.ks, c.dm}};
+                }
+            }
+        }
+        qmc_job_free(job);
+        if (rc) return rc;
+    }
+    int k = 0;
+    {
+        std::lock_guard<std::mutex> g(ctx->tune_mu);
+        for (auto &kv : best) {
+            ctx->tuned[kv.first] = kv.second.first;
+            if (choices && k < max_choices) {
+                qmc_tune_choice &ch = choices[k];
+                ch.poles = kv.second.second.first;
+                ch.width = kv.second.second.second;
+                ch.points_per_lane = kv.second.first.ppl;
+                ch.grid_per_cu = kv.second.first.grid_per_cu;
+                ch.ms = kv.second.first.ms;
+            }
+            ++k;
+        }
+    }
+    if (n_choices) *n_choices = k;
+    return QMC_OK;
 }

@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <complex>
+#include <map>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -15,6 +16,14 @@
 #include "qmc_kernels.h"
 
 struct qmc_serve_state;
+
+// Launch shape chosen by the autotuner for one kernel class.
+struct qmc_tune {
+    int ppl = 0;                     // points per lane per work item
+    int grid_per_cu = 0;             // persistent work-groups per CU (0: one per item)
+    double ms = 0.0;                 // measured time of the class
+};
+
 
 struct qmc_ctx {
     int device = 0;
@@ -27,6 +36,9 @@ struct qmc_ctx {
     std::string last_error;
     qmc_serve_state *serve = nullptr;
     std::mutex serve_mu;
+    int n_cu = 256;                  // compute units of the device
+    std::mutex tune_mu;
+    std::map<std::string, qmc_tune> tuned;   // autotuner results by class key
 };
 
 // One sector as planned: permuted exponents, term ranges, flop count.
@@ -67,13 +79,17 @@ struct qmc_plan {
     double flops_per_point = 0.0;
     qmc_sec_dev *d_sec = nullptr;
     uint32_t *d_texp = nullptr;
+    double *d_texpd = nullptr;
     uint32_t *d_dexp = nullptr;
 };
 
 struct qmc_class {                   // items launched by one kernel instance
     int ks = 0, kb = 1, deform = 0, dm = 0;
     int begin = 0, end = 0;
+    int grid = 0;                    // work-groups (0: one per item)
+    int ppl = 0;                     // lattice points per lane per item
 };
+
 
 struct qmc_job {
     qmc_ctx *ctx = nullptr;
@@ -90,17 +106,23 @@ struct qmc_job {
     int32_t *d_gbeg = nullptr, *d_gend = nullptr;
     double *d_partial = nullptr, *d_out = nullptr;
     int32_t *d_viol = nullptr, *d_gviol = nullptr;
-    std::vector<double> h_out;
-    std::vector<int32_t> h_gviol;
+    double *h_out = nullptr;         // pinned copies of the group sums
+    int32_t *h_gviol = nullptr;
+    size_t h_out_n = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> ev_cls;  // per-class timing (autotuner)
     bool launched = false;
+    bool use_graph = false;
+    hipGraphExec_t graph = nullptr;
 };
 
 int qmc_dev_alloc(qmc_ctx *ctx, void **p, size_t bytes);
 void qmc_dev_free(qmc_ctx *ctx, void *p, size_t bytes);
 int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
                   const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
-                  const double *shifts, int32_t m, int ppl_override, qmc_job **out);
+                  const double *shifts, int32_t m, int ppl_override, int grid_override,
+                  bool class_timing, qmc_job **out);
+std::string qmc_tune_key(const qmc_plan *plan, int ks, int dm, uint64_t n);
 void qmc_job_release(qmc_job *job);
 int qmc_assemble(const qmc_plan *plan, int n_points, int m, const std::vector<uint64_t> &nsec,
                  const double *gsum, qmc_result *out);

@@ -46,6 +46,18 @@ __device__ __forceinline__ T tmono(uint32_t e, const T *t, const T *t2, const T 
     return v;
 }
 
+// prod_j t_j^e_j = exp(sum_j e_j ln t_j): branch-free for wave-uniform
+// exponents (t_j > 0 wherever the real kernel evaluates a monomial)
+template <typename T>
+__device__ __forceinline__ T tmono_log(const double *e, const T *lt, int d)
+{
+    T x = 0;
+#pragma unroll
+    for (int j = 0; j < QMC_DMAX; ++j)
+        if (j < d) x = fma(T(e[j]), lt[j], x);
+    return exp(x);
+}
+
 template <typename T>
 __device__ __forceinline__ T tpowi(T x, int e)
 {
@@ -75,11 +87,11 @@ __device__ __forceinline__ void tkorobov(int r, T y, T u, T &t, T &w)
 }
 
 // Whether a sector with KS poles takes the Moebius-coefficient path
-// (cancellation-free) rather than corner values.
+// (cancellation-free) rather than corner values: every sector with a pole.
 template <typename T, int KS>
 constexpr bool use_mobius()
 {
-    return sizeof(T) == sizeof(float) ? KS >= 1 : KS >= 2;
+    return KS >= 1;
 }
 
 template <int KS, int K, typename T>
@@ -244,11 +256,10 @@ __device__ __forceinline__ void mobius_series(const qmc_sec_dev *S, Point<KS, K,
 
 // ---- kernel -------------------------------------------------------------
 
+// One work item (a tile of one (point, sector, shift) group).
 template <int KS, int K, typename T>
-__global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
+__device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, const int item_id)
 {
-    const int item_id = A.item_begin + (int)blockIdx.x;
-    if (item_id >= A.item_end) return;
     const qmc_item it = A.items[item_id];
     const qmc_sec_dev *S = A.sec + it.sector;
     const qmc_lat_dev *L = A.lat + it.lat;
@@ -283,7 +294,7 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
     for (int p = 0; p < np; ++p) {
         const uint32_t off = threadIdx.x + (uint32_t)p * QMC_BLOCK;
         if (off < it.count) {
-            T t[QMC_DMAX], t2[QMC_DMAX], t3[QMC_DMAX], w = 1;
+            T t[QMC_DMAX], lt[QMC_DMAX], w = 1;
             bool skip = false;
 #pragma unroll
             for (int j = 0; j < QMC_DMAX; ++j) {
@@ -296,8 +307,6 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
                     w *= wj;
                     skip |= (t[j] == T(0));
                 }
-                t2[j] = t[j] * t[j];
-                t3[j] = t2[j] * t[j];
             }
             if (!(w == T(0) || skip)) {
                 Point<KS, K, T> P;
@@ -306,28 +315,27 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
                 T pn = 1, LN = 0;
 #pragma unroll
                 for (int j = 0; j < QMC_DMAX; ++j) {
+                    lt[j] = 0;
                     if (j < d) {
                         constexpr int pole_lim = KS;
                         const bool pole = j < pole_lim;
                         const T bj = T(S->b[j]);
-                        if (pole || S->b[j] != 0.0 || S->aint[j] == QMC_NO_INT) {
-                            const T lt = log(t[j]);
-                            if (pole) {
-                                const int jp = pole ? j : 0;
-                                P.invt[jp] = mobius::rcp(t[j]);
-                                P.lt[jp] = lt;
-                                const T x = bj * lt;
-                                P.E[jp][0] = 1;
+                        lt[j] = log(t[j]);
+                        if (pole) {
+                            const int jp = pole ? j : 0;
+                            P.invt[jp] = mobius::rcp(t[j]);
+                            P.lt[jp] = lt[j];
+                            const T x = bj * lt[j];
+                            P.E[jp][0] = 1;
 #pragma unroll
-                                for (int q = 1; q < K; ++q)
-                                    P.E[jp][q] = P.E[jp][q - 1] * x * (T(1) / T(q));
-                            } else {
-                                LN = fma(bj, lt, LN);
-                                if (S->aint[j] == QMC_NO_INT) pn *= exp(T(S->a[j]) * lt);
-                            }
+                            for (int q = 1; q < K; ++q)
+                                P.E[jp][q] = P.E[jp][q - 1] * x * (T(1) / T(q));
+                        } else {
+                            LN = fma(bj, lt[j], LN);
+                            if (S->aint[j] == QMC_NO_INT) pn *= exp(T(S->a[j]) * lt[j]);
+                            else
+                                for (int k = 0; k < S->aint[j]; ++k) pn *= t[j];
                         }
-                        if (!pole && S->aint[j] != QMC_NO_INT)
-                            for (int k = 0; k < S->aint[j]; ++k) pn *= t[j];
                     }
                 }
                 P.LN = LN;
@@ -336,9 +344,9 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
                 for (int m = 0; m < (1 << KS); ++m) {
                     T su = 0, sf = 0;
                     for (int q = S->um[m]; q < S->um[m + 1]; ++q)
-                        su = fma(T(coef[q]), tmono<T>(A.texp[q], t, t2, t3), su);
+                        su = fma(T(coef[q]), tmono_log<T>(A.texpd + q * QMC_DMAX, lt, d), su);
                     for (int q = S->fm[m]; q < S->fm[m + 1]; ++q)
-                        sf = fma(T(coef[q]), tmono<T>(A.texp[q], t, t2, t3), sf);
+                        sf = fma(T(coef[q]), tmono_log<T>(A.texpd + q * QMC_DMAX, lt, d), sf);
                     P.SU[m] = su;
                     P.SF[m] = sf;
                 }
@@ -378,6 +386,19 @@ __global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
     double *dst = A.partial + (size_t)item_id * A.kstride * 4;
     block_reduce_store<K, 1>(acc, cmp, dst, A.kstride);
     store_violations(viol, A.viol + item_id);
+}
+
+// Work-groups take items item_begin + blockIdx.x, + gridDim.x, ...: one item
+// per work-group when the grid covers the list, a persistent loop when the
+// grid is smaller.  Each item writes only its own slot, so the result does
+// not depend on the grid.
+template <int KS, int K, typename T>
+__global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
+{
+    for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
+        qmc_eval_real_item<KS, K, T>(A, item);
+        __syncthreads();
+    }
 }
 
 } // namespace qmc_real

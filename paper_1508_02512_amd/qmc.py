@@ -71,6 +71,11 @@ class qmc_result(C.Structure):
                 ("latency_ms", C.c_double), ("steps", C.c_int32), ("reserved", C.c_int32)]
 
 
+class qmc_tune_choice(C.Structure):
+    _fields_ = [("poles", C.c_int32), ("width", C.c_int32), ("points_per_lane", C.c_int32),
+                ("grid_per_cu", C.c_int32), ("ms", C.c_double)]
+
+
 class qmc_request(C.Structure):
     _fields_ = [("kin", P(C.c_double)), ("rel_err_target", C.c_double), ("n0", C.c_uint64),
                 ("n_max", C.c_uint64), ("m", C.c_int32), ("seed", C.c_uint64),
@@ -95,6 +100,10 @@ _SIGS = {
     "qmc_run": (C.c_int, [C.c_void_p]),
     "qmc_fetch": (C.c_int, [C.c_void_p, P(qmc_result)]),
     "qmc_job_free": (None, [C.c_void_p]),
+    "qmc_job_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
+    "qmc_autotune": (C.c_int, [C.c_void_p, C.c_void_p, P(C.c_double), C.c_int32,
+                               P(qmc_lattice), P(qmc_lattice), P(C.c_double), C.c_int32,
+                               P(qmc_tune_choice), C.c_int32, P(C.c_int32)]),
     "qmc_submit": (C.c_int, [C.c_void_p, C.c_void_p, P(qmc_request), P(C.c_uint64)]),
     "qmc_poll": (C.c_int, [C.c_void_p, C.c_uint64, P(qmc_result)]),
     "qmc_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double, P(qmc_result)]),
@@ -295,6 +304,17 @@ class Plan:
     def bind(self, kin, lattice, shifts, lat_per_sector=None):
         return Job(self, kin, lattice, shifts, lat_per_sector)
 
+    def autotune(self, kin, lattice, shifts, lat_per_sector=None):
+        """Time launch shapes per kernel class; later binds use the best."""
+        kin, shifts, lat, lps = self._inputs(kin, lattice, shifts, lat_per_sector)
+        ch = (qmc_tune_choice * 64)()
+        n = C.c_int32()
+        self.ctx.check(lib().qmc_autotune(self.ctx.h, self.h, _dptr(kin), kin.shape[0],
+                                          C.byref(lat) if lat is not None else None, lps,
+                                          _dptr(shifts), shifts.shape[0], ch, 64, C.byref(n)))
+        return [{"poles": c.poles, "width": c.width, "points_per_lane": c.points_per_lane,
+                 "grid_per_cu": c.grid_per_cu, "ms": c.ms} for c in ch[:min(n.value, 64)]]
+
 
 class Request:
     """Handle of one served request (continuous batching, see qmc.h)."""
@@ -360,6 +380,9 @@ class Job:
     def run(self):
         self.plan.ctx.check(lib().qmc_run(self.h))
 
+    def use_graph(self, enable=True):
+        self.plan.ctx.check(lib().qmc_job_set_graph(self.h, int(enable)))
+
     def fetch(self, sector_sums=False, per_shift=False):
         n_points, m = self.kin.shape[0], self.shifts.shape[0]
         res, coeff, ss, ps = self.plan._result(n_points, m, sector_sums, per_shift)
@@ -376,3 +399,27 @@ class Job:
             self.close()
         except Exception:
             pass
+
+
+def size_lattices(plan, kin, total_points, primes, pilot_n, pilot_z, shifts, cost=None):
+    """Per-sector lattice sizes for a fixed total budget of lattice points.
+
+    A pilot run at n = pilot_n gives each sector's spread c_s over the shifts
+    (largest over Laurent orders).  With a QMC error ~ c_s / n_s and a cost
+    ~ cost_s n_s, minimising the summed variance sum_s (c_s / n_s)^2 for the
+    budget gives n_s proportional to (c_s^2 / cost_s)^(1/3); sizes are then
+    rounded (in log scale) to the nearest available prime."""
+    pilot = plan.integrate(kin, (pilot_n, pilot_z), shifts, sector_sums=True)
+    ss = pilot["sector_sums"][0] / float(pilot_n)          # [sectors][m][orders]
+    spread = np.abs(ss - ss.mean(axis=1, keepdims=True)).max(axis=(1, 2))
+    spread = np.maximum(spread, 1e-30)
+    cost = np.ones_like(spread) if cost is None else np.asarray(cost, dtype=float)
+    w = np.cbrt(spread ** 2 / cost)
+    share = w / w.sum()
+    want = share * float(total_points)
+    primes = np.asarray(sorted(primes))
+    out = []
+    for v in want:
+        i = int(np.argmin(np.abs(np.log(primes) - np.log(max(v, primes[0])))))
+        out.append(int(primes[i]))
+    return out

@@ -1,0 +1,79 @@
+"""Batching: many kinematic points x all sectors with uneven lattice sizes,
+persistent grids, graph replay and the autotuner."""
+
+import numpy as np
+import pytest
+
+from gpu_util import ctx, gpu_plan
+from oracle import qmc as oq
+from oracle.decompose import decompose as odec
+from paper_1508_02512_amd import frontend as fe
+from paper_1508_02512_amd import qmc
+from seeded_inputs.lattice import lattice
+from seeded_inputs.problems import PROBLEMS
+from seeded_inputs.rng import shift_table
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1009, 4099, 10007, 65521]
+
+
+def _batch(n_points=24, seed=0):
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(-10, 10, size=4 * n_points)
+    s = s[np.abs(s - 4.0) >= 0.05][:n_points]
+    return s
+
+
+def _inputs(plan, info, svals):
+    kin = np.stack([fe.kin_vector(info, {"s": float(v), "msq": 1.0}) for v in svals])
+    lats = [(n, lattice(n)) for n in (SIZES[i % len(SIZES)] for i in range(plan.n_sectors))]
+    return kin, lats
+
+
+def test_batch_parity_graph_and_grid():
+    print("batch: triangle2l 24 points, uneven lattices", flush=True)
+    plan, info = gpu_plan("triangle2l", lam=0.5)
+    svals = _batch()
+    kin, lats = _inputs(plan, info, svals)
+    sh = shift_table(5, 3, 8)
+    eager = plan.integrate(kin, None, sh, lat_per_sector=lats, sector_sums=True)
+    assert eager["violations"] == 0
+    # persistent grids and graph replay give the same bits
+    job = plan.bind(kin, None, sh, lat_per_sector=lats)
+    job.use_graph(True)
+    for rep in range(4):
+        job.run()
+        got = job.fetch(sector_sums=True)
+        np.testing.assert_array_equal(got["sector_sums"], eager["sector_sums"])
+        # eager work between replays
+        plan.integrate(kin[:2], None, sh, lat_per_sector=lats)
+    job.close()
+    # oracle on sampled (point, sector) pairs
+    osecs, oinfo = odec(PROBLEMS["triangle2l"])
+    rng = np.random.default_rng(1)
+    for p in rng.choice(len(svals), size=4, replace=False):
+        for s in rng.choice(len(osecs), size=4, replace=False):
+            ns = oq.NumericSector(osecs[s], oinfo, {"s": float(svals[p]), "msq": 1.0})
+            n, z = lats[s]
+            sums, abss, _ = oq.sector_sums(ns, n, z, sh, 2, oq.effective_lambda(ns, 0.5),
+                                           eager["sec_lo"], plan.info.sec_orders)
+            scale = abss[..., 0] + abss[..., 1]
+            err = np.abs(eager["sector_sums"][p, s] - sums)
+            assert np.all(err <= 1e-12 * np.maximum(scale, 1e-300)), (p, s)
+    plan.close()
+
+
+def test_autotune_then_same_result():
+    print("batch: autotune", flush=True)
+    plan, info = gpu_plan("triangle2l", lam=0.5)
+    svals = _batch(8, seed=3)
+    kin, lats = _inputs(plan, info, svals)
+    sh = shift_table(6, 2, 8)
+    before = plan.integrate(kin, None, sh, lat_per_sector=lats, sector_sums=True)
+    choices = plan.autotune(kin, None, sh, lat_per_sector=lats)
+    assert choices and all(c["points_per_lane"] > 0 for c in choices)
+    after = plan.integrate(kin, None, sh, lat_per_sector=lats, sector_sums=True)
+    b, a = before["sector_sums"], after["sector_sums"]
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-13 * np.max(np.abs(b)))
+    plan.close()
