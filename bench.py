@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-time-to-target", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--extra", action="store_true",
+                    help="also run the non-planar vertex and the 512-point batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM counters)")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -139,6 +141,81 @@ def serve_bench(qmc, fe, PROBLEMS, lattice, seconds, rate, fp32, slots, log):
     return res
 
 
+def vertex_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, n_total=10000019):
+    """Non-planar two-loop vertex with a massive loop, s = 4.5 (physical),
+    lambda = 0.5, 32 shifts, per-sector lattice sizes from a pilot run."""
+    import numpy as np
+    import torch
+
+    from seeded_inputs.lattice import PRIME_SIZES
+    secs, info = fe.decompose(PROBLEMS["np_vertex"])
+    plan = ctx.plan(fe.sector_arrays(secs, info), info, 0, fe.prefactor_series(info, 12),
+                    lam=0.5)
+    kin = fe.kin_vector(info, {"s": 4.5, "msq": 1.0})
+    sh = shift_table(0, 32, 8)
+    sizes = qmc.size_lattices(plan, kin, n_total * plan.n_sectors, PRIME_SIZES, 65521,
+                              lattice(65521), shift_table(1, 8, 8))
+    lats = [(n, lattice(n)) for n in sizes]
+    job = plan.bind(kin, None, sh, lat_per_sector=lats)
+    job.run()
+    job.fetch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    job.run()
+    r = job.fetch()
+    wall = time.perf_counter() - t0
+    job.close()
+    plan.close()
+    out = {"value": r["evals"] / wall, "unit": "evals/s", "seconds": wall,
+           "kernel_ms": r["kernel_ms"], "achieved_tflops": r["algo_flops"] / r["kernel_ms"] / 1e9,
+           "eps0": [float(r["mean"][0, -1].real), float(r["mean"][0, -1].imag)],
+           "err": [float(r["err_re"][0, -1]), float(r["err_im"][0, -1])],
+           "violations": int(r["violations"]), "n_min": min(sizes), "n_max": max(sizes)}
+    log(f"np_vertex: {out['value']:.3e} evals/s, eps^0 = {out['eps0']} +- {out['err']}")
+    return out
+
+
+def batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, fp32):
+    """512 kinematic points of the all-massive two-loop planar vertex,
+    s uniform in [-10, 10] without |s - 4| < 0.05 (numpy PCG64 seed 0),
+    every sector with its own lattice size (100003 .. 10000019), one
+    autotuned, graph-replayed launch sequence."""
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(0)
+    svals = []
+    while len(svals) < 512:
+        v = float(rng.uniform(-10.0, 10.0))
+        if abs(v - 4.0) >= 0.05:
+            svals.append(v)
+    secs, info = fe.decompose(PROBLEMS["triangle2l"])
+    prec = qmc.QMC_FP32_EVAL if fp32 else qmc.QMC_FP64
+    plan = ctx.plan(fe.sector_arrays(secs, info), info, 0, fe.prefactor_series(info, 12),
+                    lam=0.25, precision=prec)
+    kin = np.stack([fe.kin_vector(info, {"s": v, "msq": 1.0}) for v in svals])
+    tiers = [100003, 1000003, 10000019]
+    lats = [(n, lattice(n)) for n in (tiers[i % 3] for i in range(plan.n_sectors))]
+    sh = shift_table(0, 4, 8)
+    choices = plan.autotune(kin[:8], None, shift_table(0, 2, 8), lat_per_sector=lats)
+    job = plan.bind(kin, None, sh, lat_per_sector=lats)
+    job.use_graph(True)
+    job.run()
+    job.fetch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    job.run()
+    r = job.fetch()
+    wall = time.perf_counter() - t0
+    job.close()
+    plan.close()
+    out = {"value": r["evals"] / wall, "unit": "evals/s", "seconds": wall,
+           "precision": "fp32-eval" if fp32 else "fp64", "points": len(svals),
+           "autotune": choices, "violations": int(r["violations"])}
+    log(f"batch ({out['precision']}): {out['value']:.3e} evals/s in {wall:.2f} s")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -170,6 +247,7 @@ def main():
     kin = fe.kin_vector(info, kin_vals)
     n, m = args.n, args.shifts
     job = plan.bind(kin, (n, lattice(n)), shift_table(0, m, 8))
+    job.profile(True)          # HIP events around every kernel-class launch
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"bench: {plan.n_sectors} sectors, n={n}, m={m}, warmup {args.warmup}")
@@ -177,19 +255,27 @@ def main():
         job.run()
         job.fetch()
     torch.cuda.synchronize()
-    kernel_ms = []
+    kernel_ms, step_stats = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         job.run()
         res = job.fetch()
         kernel_ms.append(res["kernel_ms"])
+        step_stats.append(job.class_stats())
         log(f"step {len(kernel_ms)}: kernels {res['kernel_ms']:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     evals_per_step = res["evals"]
     value = evals_per_step * args.steps / wall
     avg_kernel_s = float(np.mean(kernel_ms)) / 1e3
-    achieved = res["algo_flops"] / avg_kernel_s
+    achieved_step = res["algo_flops"] / avg_kernel_s
+    # dominant kernel: the class launch with the largest share of the step,
+    # its time averaged over the timed steps
+    stats = step_stats
+    dom = max(range(len(stats[0])), key=lambda i: stats[0][i]["ms"])
+    dom_ms = float(np.mean([st[dom]["ms"] for st in stats]))
+    dom_stat = stats[0][dom]
+    achieved = dom_stat["algo_flops"] / (dom_ms / 1e3)
 
     def time_to_target(pl, label):
         """Wall time of the prime-lattice doubling until every order has
@@ -244,6 +330,14 @@ def main():
         plan32.close()
         log(f"fp32: {fp32['value']:.3e} evals/s")
 
+    extra = None
+    if args.extra:
+        extra = {"np_vertex": vertex_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log),
+                 "batch_fp64": batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log,
+                                           False),
+                 "batch_fp32": batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log,
+                                           True)}
+
     serve = None
     if not args.no_serve:
         serve = {
@@ -272,11 +366,25 @@ def main():
                    "evals_per_step": evals_per_step, "precision": "fp64"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-                     "kernel_ms_per_step": avg_kernel_s * 1e3,
-                     "algo_flops_per_step": res["algo_flops"]},
+                     "kernel": f"qmc_eval_real<poles={dom_stat['poles']}, double>"
+                               if dom_stat["width"] == 0 else
+                               f"qmc_eval_cplx<width={dom_stat['width']}, "
+                               f"poles={dom_stat['poles']}>",
+                     "launch_ms": dom_ms, "algo_flops_per_launch": dom_stat["algo_flops"],
+                     "evals_per_launch": dom_stat["evals"],
+                     "grid": dom_stat["grid"], "points_per_lane": dom_stat["points_per_lane"],
+                     "step": {"kernel_ms": avg_kernel_s * 1e3,
+                              "algo_flops": res["algo_flops"],
+                              "achieved": achieved_step / 1e12,
+                              "frac": achieved_step / PEAK_FP64_VALU,
+                              "launches": [{"poles": c["poles"], "width": c["width"],
+                                            "ms": c["ms"], "tflops": c["algo_flops"] /
+                                            max(c["ms"], 1e-9) / 1e9}
+                                           for c in stats[-1]]}},
         "time_to_1e-3": ttt,
         "fp32_eval": fp32,
         "serve": serve,
+        "extra": extra,
         "result_eps0": [float(res["mean"][0, -1].real), float(res["err_re"][0, -1])],
     }
     if not args.no_cpu_baseline:

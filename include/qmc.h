@@ -200,10 +200,48 @@ typedef struct {
 } qmc_tune_choice;
 
 int qmc_job_set_graph(qmc_job *job, int enable);
+
+/* Per-kernel accounting of a bound job.  Each class of work items (poles,
+ * complex width) is one kernel launch per qmc_run.  qmc_job_set_profiling
+ * with enable != 0 records a HIP event pair around every class launch of
+ * later eager runs (not inside a graph); qmc_job_class_stats copies up to
+ * max entries, one per class in launch order, and sets *n to the number of
+ * classes.  ms is the event time of that launch in the last completed eager
+ * run (after qmc_fetch), -1 when it was not timed.  algo_flops counts the
+ * algorithmic FP64 (or FP32) operations of the launch with the convention
+ * add/mul 1, fma 2, division and log/exp 20 per lattice point of Eq. 16's
+ * inner sum, summed over the launch's points.  Errors: QMC_EINVAL on a null
+ * job or n. */
+typedef struct {
+    int32_t poles, width;        /* class: poles, complex width (0 = real) */
+    int32_t points_per_lane;     /* tile of one item is 256 * points_per_lane */
+    int32_t grid;                /* work-groups launched */
+    int32_t items;               /* work items in the class */
+    int32_t precision;           /* QMC_FP64 or QMC_FP32_EVAL */
+    uint64_t evals;              /* integrand evaluations of one launch */
+    double algo_flops;           /* algorithmic flops of one launch */
+    double ms;                   /* launch time of the last eager run, or -1 */
+} qmc_class_stat;
+
+int qmc_job_set_profiling(qmc_job *job, int enable);
+int qmc_job_class_stats(const qmc_job *job, qmc_class_stat *out, int32_t max, int32_t *n);
+
 int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
                  const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
                  const double *shifts, int32_t m, qmc_tune_choice *choices,
                  int32_t max_choices, int32_t *n_choices);
+
+/* ---- diagnostics -------------------------------------------------------------
+ * qmc_math_eval applies one of the elementary functions that the integrand
+ * kernels use for the logarithms of Eq. 9's factors, the monomials of U and
+ * F and the eps expansion (fn: QMC_MATH_LN for x > 0, QMC_MATH_LN1P for
+ * x > -1, QMC_MATH_EXP and QMC_MATH_EXPM1 for finite x) to n doubles x
+ * (device) and writes y (device, n doubles) on the context stream, then
+ * waits for it.  Outside those domains the result is unspecified.  For tests
+ * that bound their error.  Errors: QMC_EINVAL (null pointer, n < 0, unknown
+ * fn), QMC_EDEVICE. */
+enum { QMC_MATH_LN = 0, QMC_MATH_LN1P = 1, QMC_MATH_EXP = 2, QMC_MATH_EXPM1 = 3 };
+int qmc_math_eval(qmc_ctx *ctx, int32_t fn, const double *x, double *y, int64_t n);
 
 /* ---- serving (continuous batching) ---------------------------------------
  * A request is one integral (a plan) at one kinematic point with a relative

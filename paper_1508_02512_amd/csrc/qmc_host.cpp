@@ -150,7 +150,7 @@ static uint32_t pack_exps(const uint8_t *e, const int *perm, int dim)
 // Algorithmic FP64 flops of one lattice point of one sector (see DESIGN
 // notes in the library documentation): add/sub/mul = 1, fma = 2, division
 // and each log/exp/atan = 20.
-static double sector_flops(const qmc_sec_host &h)
+static double sector_flops(const qmc_sec_host &h, bool deform)
 {
     const double T = 20.0;
     const int d = h.dim, ks = h.ks, K = h.K;
@@ -171,7 +171,7 @@ static double sector_flops(const qmc_sec_host &h)
     f += ks * (T + 3.0 * (K - 1));              // 1/t and (b ln t)^r / r!
     f += (corners - 1) * (K + K * (K - 1) + 3.0 * K);   // folds
     f += K * (2 + 4);                           // weight and Neumaier
-    if (h.deform) {
+    if (deform) {
         const int nd = (int)h.dterm_nnz.size();
         double dterms = 0;
         for (int v : h.dterm_nnz) dterms += v + 2;
@@ -400,7 +400,8 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
             h.d2[idx] = (int32_t)plan->dexp.size();
         }
         h.D = std::complex<double>(S.coef_re, S.coef_im);
-        h.flops = sector_flops(h);
+        h.flops = sector_flops(h, false);
+        h.flops_deform = h.deform ? sector_flops(h, true) : h.flops;
         plan->flops_per_point += h.flops;
         plan->secs.push_back(h);
     }
@@ -712,6 +713,9 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
                         it.count = (uint32_t)std::min<uint64_t>(tile, n - st);
                         it.stride = 1;
                         items.push_back(it);
+                        c.evals += it.count;
+                        c.flops += it.count * (c.dm ? plan->secs[s].flops_deform
+                                                    : plan->secs[s].flops);
                     }
                     gend[g] = (int32_t)items.size();
                 }
@@ -842,6 +846,7 @@ extern "C" int qmc_run(qmc_job *job)
         HIP_CHECK(ctx, hipEventRecord(job->ev0, ctx->stream));
         HIP_CHECK(ctx, enqueue(true));
     }
+    job->cls_timed = !job->use_graph && !job->ev_cls.empty();
     job->launched = true;
     return QMC_OK;
 }
@@ -943,9 +948,15 @@ extern "C" int qmc_fetch(qmc_job *job, qmc_result *out)
     out->status = viol ? QMC_EDEFORM : QMC_OK;
     out->kernel_ms = ms;
     double fl = 0.0;
-    for (size_t s = 0; s < job->plan->secs.size(); ++s)
-        fl += job->plan->secs[s].flops * (double)job->n_per_sector[s];
-    out->algo_flops = fl * job->m * job->n_points;
+    for (const qmc_class &c : job->classes) fl += c.flops;
+    out->algo_flops = fl;
+    job->cls_ms.assign(job->classes.size(), -1.0);
+    if (job->cls_timed)
+        for (size_t i = 0; i < job->classes.size(); ++i) {
+            float cms = 0.0f;
+            if (hipEventElapsedTime(&cms, job->ev_cls[i], job->ev_cls[i + 1]) == hipSuccess)
+                job->cls_ms[i] = cms;
+        }
     return out->status == QMC_OK ? QMC_OK
                                  : set_err(ctx, out->status, "%ld points violated the sign conditions", viol);
 }
@@ -982,6 +993,62 @@ extern "C" int qmc_job_set_graph(qmc_job *job, int enable)
         (void)hipGraphExecDestroy(job->graph);
         job->graph = nullptr;
     }
+    return QMC_OK;
+}
+
+extern "C" int qmc_job_set_profiling(qmc_job *job, int enable)
+{
+    if (!job) return QMC_EINVAL;
+    if (job->launched) return set_err(job->ctx, QMC_EINVAL, "job is running");
+    (void)hipSetDevice(job->ctx->device);
+    for (hipEvent_t e : job->ev_cls) (void)hipEventDestroy(e);
+    job->ev_cls.clear();
+    job->cls_timed = false;
+    if (enable) {
+        job->ev_cls.resize(job->classes.size() + 1, nullptr);
+        for (auto &e : job->ev_cls)
+            if (hipEventCreate(&e) != hipSuccess) {
+                for (hipEvent_t x : job->ev_cls)
+                    if (x) (void)hipEventDestroy(x);
+                job->ev_cls.clear();
+                return set_err(job->ctx, QMC_EDEVICE, "event creation failed");
+            }
+    }
+    return QMC_OK;
+}
+
+extern "C" int qmc_job_class_stats(const qmc_job *job, qmc_class_stat *out, int32_t max,
+                                   int32_t *n)
+{
+    if (!job || !n) return QMC_EINVAL;
+    const int nc = (int)job->classes.size();
+    for (int i = 0; i < nc && out && i < max; ++i) {
+        const qmc_class &c = job->classes[i];
+        const int items = c.end - c.begin;
+        qmc_class_stat &st = out[i];
+        st.poles = c.ks;
+        st.width = c.dm;
+        st.points_per_lane = c.ppl;
+        st.grid = c.grid > 0 ? std::min(c.grid, items) : items;
+        st.items = items;
+        st.precision = job->plan->opts.precision;
+        st.evals = c.evals;
+        st.algo_flops = c.flops;
+        st.ms = (size_t)i < job->cls_ms.size() ? job->cls_ms[i] : -1.0;
+    }
+    *n = nc;
+    return QMC_OK;
+}
+
+extern "C" int qmc_math_eval(qmc_ctx *ctx, int32_t fn, const double *x, double *y,
+                             int64_t n)
+{
+    if (!ctx) return QMC_EINVAL;
+    if (n < 0 || fn < QMC_MATH_LN || fn > QMC_MATH_EXPM1 || (n > 0 && (!x || !y)))
+        return set_err(ctx, QMC_EINVAL, "qmc_math_eval: bad argument");
+    (void)hipSetDevice(ctx->device);
+    HIP_CHECK(ctx, qmc_launch_math(fn, x, y, (long)n, ctx->stream));
+    HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
     return QMC_OK;
 }
 

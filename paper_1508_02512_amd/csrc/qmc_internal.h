@@ -57,6 +57,7 @@ struct qmc_sec_host {
     std::vector<int> term_nnz;   // non-zero exponents per term (U and F)
     std::vector<int> dterm_nnz;  // the same for the derivative terms
     double flops = 0.0;          // algorithmic flops per lattice point
+    double flops_deform = 0.0;   // the same on a deformed contour
     qmc_sec_dev dev() const;
 };
 
@@ -88,6 +89,8 @@ struct qmc_class {                   // items launched by one kernel instance
     int begin = 0, end = 0;
     int grid = 0;                    // work-groups (0: one per item)
     int ppl = 0;                     // lattice points per lane per item
+    uint64_t evals = 0;              // integrand evaluations of one launch
+    double flops = 0.0;              // algorithmic flops of one launch
 };
 
 
@@ -110,7 +113,9 @@ struct qmc_job {
     int32_t *h_gviol = nullptr;
     size_t h_out_n = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::vector<hipEvent_t> ev_cls;  // per-class timing (autotuner)
+    std::vector<hipEvent_t> ev_cls;  // per-class timing (autotuner, profiling)
+    bool cls_timed = false;          // the last run recorded ev_cls
+    std::vector<double> cls_ms;      // per-class times of the last fetched run
     bool launched = false;
     bool use_graph = false;
     hipGraphExec_t graph = nullptr;

@@ -23,3 +23,6 @@ hipError_t qmc_launch_reduce(const double *partial, const int32_t *viol,
                              const int32_t *group_begin, const int32_t *group_end,
                              int n_groups, int kstride, double *out, int32_t *gviol,
                              hipStream_t stream);
+
+// qmc_math::ln, ln1p, ex, exm1 (fn = 0..3) applied to n device values.
+hipError_t qmc_launch_math(int fn, const double *x, double *y, long n, hipStream_t stream);

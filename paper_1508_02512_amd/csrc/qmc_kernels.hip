@@ -5,6 +5,7 @@
 #include "qmc_common.h"
 #include "qmc_device.h"
 #include "qmc_kernels.h"
+#include "qmc_math.h"
 
 using namespace qmc;
 
@@ -61,5 +62,31 @@ hipError_t qmc_launch_reduce(const double *partial, const int32_t *viol,
     hipLaunchKernelGGL(qmc_reduce_groups, dim3(blocks), dim3(threads), 0, stream,
                        partial, viol, group_begin, group_end, n_groups, kstride, out,
                        gviol);
+    return hipGetLastError();
+}
+
+// Elementary functions of the integrand kernels on an array (diagnostics).
+__global__ void qmc_math_kernel(int fn, const double *x, double *y, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = x[i];
+    double r = 0.0;
+    switch (fn) {
+    case 0: r = qmc_math::ln(v); break;
+    case 1: r = qmc_math::ln1p(v); break;
+    case 2: r = qmc_math::ex(v); break;
+    default: r = qmc_math::exm1(v); break;
+    }
+    y[i] = r;
+}
+
+hipError_t qmc_launch_math(int fn, const double *x, double *y, long n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int threads = 256;
+    const long blocks = (n + threads - 1) / threads;
+    hipLaunchKernelGGL(qmc_math_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, fn,
+                       x, y, n);
     return hipGetLastError();
 }

@@ -24,6 +24,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "qmc_math.h"
+
 namespace mobius {
 
 // reciprocal to ~1 ulp: hardware estimate and Newton steps
@@ -103,8 +105,9 @@ __device__ __forceinline__ void div(const T (&a)[1 << KS], const T (&b)[1 << KS]
     }
 }
 
-// r = log(1 + x)
-template <int KS, typename T>
+// r = log(1 + x); with X0ZERO the caller guarantees x^[0] = 0, so the
+// leaf on the empty set is 0 and is not evaluated
+template <int KS, typename T, bool X0ZERO = false>
 struct Log1p {
     static __device__ __forceinline__ void run(const T (&x)[1 << KS], T (&r)[1 << KS])
     {
@@ -117,9 +120,9 @@ struct Log1p {
             d[W] = x[W];
         }
         d[0] += T(1);
-        Log1p<KS - 1, T>::run(x0, r0);
+        Log1p<KS - 1, T, X0ZERO>::run(x0, r0);
         div<KS - 1, T>(x1, d, y);
-        Log1p<KS - 1, T>::run(y, r1);
+        Log1p<KS - 1, T, false>::run(y, r1);
 #pragma unroll
         for (int W = 0; W < H; ++W) {
             r[W] = r0[W];
@@ -128,11 +131,11 @@ struct Log1p {
     }
 };
 
-template <typename T>
-struct Log1p<0, T> {
+template <typename T, bool X0ZERO>
+struct Log1p<0, T, X0ZERO> {
     static __device__ __forceinline__ void run(const T (&x)[1], T (&r)[1])
     {
-        r[0] = log1p(x[0]);
+        r[0] = X0ZERO ? T(0) : qmc_math::ln1p(x[0]);
     }
 };
 
@@ -146,41 +149,12 @@ __device__ __forceinline__ void log(const T (&f)[1 << KS], T (&r)[1 << KS])
     x[0] = 0;
 #pragma unroll
     for (int Y = 1; Y < N; ++Y) x[Y] = f[Y] * inv0;
-    Log1p<KS, T>::run(x, r);
-    r[0] = ::log(f[0]);
+    Log1p<KS, T, true>::run(x, r);
+    r[0] = qmc_math::ln(f[0]);
 }
 
-// r = f^e for an integer e (wave-uniform)
-template <int KS, typename T>
-__device__ __forceinline__ void powi(const T (&f)[1 << KS], int e, T (&r)[1 << KS])
-{
-    constexpr int N = 1 << KS;
-    T base[N], one[N];
-#pragma unroll
-    for (int Y = 0; Y < N; ++Y) {
-        one[Y] = Y == 0 ? T(1) : T(0);
-        r[Y] = one[Y];
-    }
-    if (e == 0) return;
-    if (e < 0) {
-        div<KS, T>(one, f, base);
-        e = -e;
-    } else {
-#pragma unroll
-        for (int Y = 0; Y < N; ++Y) base[Y] = f[Y];
-    }
-#pragma unroll
-    for (int Y = 0; Y < N; ++Y) r[Y] = base[Y];
-    for (int k = 1; k < e; ++k) {
-        T tmp[N];
-        mul<KS, KS, T>(r, base, tmp);
-#pragma unroll
-        for (int Y = 0; Y < N; ++Y) r[Y] = tmp[Y];
-    }
-}
-
-// r = exp(x) - 1
-template <int KS, typename T>
+// r = exp(x) - 1; with X0ZERO the caller guarantees x^[0] = 0
+template <int KS, typename T, bool X0ZERO = false>
 struct Expm1 {
     static __device__ __forceinline__ void run(const T (&x)[1 << KS], T (&r)[1 << KS])
     {
@@ -191,8 +165,8 @@ struct Expm1 {
             x0[W] = x[W];
             x1[W] = x[W + H];
         }
-        Expm1<KS - 1, T>::run(x0, r0);
-        Expm1<KS - 1, T>::run(x1, r1);
+        Expm1<KS - 1, T, X0ZERO>::run(x0, r0);
+        Expm1<KS - 1, T, false>::run(x1, r1);
 #pragma unroll
         for (int W = 0; W < H; ++W) e0[W] = r0[W];
         e0[0] += T(1);
@@ -205,11 +179,11 @@ struct Expm1 {
     }
 };
 
-template <typename T>
-struct Expm1<0, T> {
+template <typename T, bool X0ZERO>
+struct Expm1<0, T, X0ZERO> {
     static __device__ __forceinline__ void run(const T (&x)[1], T (&r)[1])
     {
-        r[0] = expm1(x[0]);
+        r[0] = X0ZERO ? T(0) : qmc_math::exm1(x[0]);
     }
 };
 
@@ -222,8 +196,8 @@ __device__ __forceinline__ void exp(const T (&x)[1 << KS], T (&r)[1 << KS])
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) y[Y] = x[Y];
     y[0] = 0;
-    Expm1<KS, T>::run(y, e);
-    const T s = ::exp(x[0]);
+    Expm1<KS, T, true>::run(y, e);
+    const T s = qmc_math::ex(x[0]);
     e[0] += T(1);
 #pragma unroll
     for (int Y = 0; Y < N; ++Y) r[Y] = s * e[Y];

@@ -17,6 +17,7 @@
 
 #include "qmc_common.h"
 #include "qmc_device.h"
+#include "qmc_math.h"
 #include "qmc_mobius.h"
 
 namespace qmc_real {
@@ -55,7 +56,7 @@ __device__ __forceinline__ T tmono_log(const double *e, const T *lt, int d)
 #pragma unroll
     for (int j = 0; j < QMC_DMAX; ++j)
         if (j < d) x = fma(T(e[j]), lt[j], x);
-    return exp(x);
+    return qmc_math::ex(x);
 }
 
 template <typename T>
@@ -114,12 +115,12 @@ __device__ __forceinline__ void leaf(const qmc_sec_dev *S, Point<KS, K, T> &P, i
     const T u = P.SU[full ^ X];
     const T f = P.SF[full ^ X];
     P.bad |= !(u > T(0)) | !(f > T(0));
-    const T lu = log(u), lf = log(f);
+    const T lu = qmc_math::ln(u), lf = qmc_math::ln(f);
     T pre;
     if (S->u0i != QMC_NO_INT && S->f0i != QMC_NO_INT)
         pre = tpowi(u, S->u0i) * tpowi(f, S->f0i);
     else
-        pre = exp(T(S->u0) * lu + T(S->f0) * lf);
+        pre = qmc_math::ex(T(S->u0) * lu + T(S->f0) * lf);
     const T L = fma(T(S->u1), lu, fma(T(S->f1), lf, P.LN));
     h[0] = pre;
 #pragma unroll
@@ -167,12 +168,14 @@ struct Tree<0, XB, KS, K, T> {
 
 // ---- Moebius path -----------------------------------------------------------
 
-// g[q + r + |Y|] += CY[Y] LY[Y]^r / r! h_q^[Y] for each order q of h, with
-// h_{q+1} = h_q B / (q + 1) formed only on the subsets that still contribute.
+// g[q + r + |Y|] += C(Y) L(Y)^r / r! h_q^[Y] for each order q of h, with
+// h_{q+1} = h_q B / (q + 1) formed only on the subsets that still
+// contribute, C(Y) = prod_{j in Y} t_j^-1 prod_{j not in Y} 1/b_j and
+// L(Y) = sum_{j in Y} b_j ln t_j (formed where used: fewer live registers).
 template <int KS, int K, int Q, typename T>
 struct Accum {
-    static __device__ __forceinline__ void run(const T (&B)[1 << KS], T (&H)[1 << KS],
-                                               const T (&CY)[1 << KS], const T (&LY)[1 << KS],
+    static __device__ __forceinline__ void run(const qmc_sec_dev *S, const Point<KS, K, T> &P,
+                                               const T (&B)[1 << KS], T (&H)[1 << KS],
                                                T (&g)[K])
     {
         constexpr int N = 1 << KS;
@@ -180,13 +183,23 @@ struct Accum {
         for (int Y = 0; Y < N; ++Y) {
             const int pc = __builtin_popcount(Y);
             if (Q + pc >= K) continue;
-            T e = CY[Y] * H[Y];
+            T c = 1, L = 0;
+#pragma unroll
+            for (int j = 0; j < KS; ++j) {
+                if (Y >> j & 1) {
+                    c *= P.invt[j];
+                    L = fma(T(S->b[j]), P.lt[j], L);
+                } else {
+                    c *= T(S->inv_b[j]);
+                }
+            }
+            T e = c * H[Y];
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 const int o = Q + r + pc;
                 if (o < K) {
                     g[o] += e;
-                    e *= LY[Y] * (T(1) / T(r + 1));
+                    e *= L * (T(1) / T(r + 1));
                 }
             }
         }
@@ -197,14 +210,14 @@ struct Accum {
 #pragma unroll
             for (int Y = 0; Y < N; ++Y)
                 H[Y] = __builtin_popcount(Y) <= MAXPC ? nt[Y] * (T(1) / T(Q + 1)) : T(0);
-            Accum<KS, K, Q + 1, T>::run(B, H, CY, LY, g);
+            Accum<KS, K, Q + 1, T>::run(S, P, B, H, g);
         }
     }
 };
 
 // The subtracted integrand from Moebius coefficients (see qmc_mobius.h):
-// h = U^(u0+u1 eps) F^(f0+f1 eps) exp(eps LN) = Pre exp(eps B) with
-// B = u1 log U + f1 log F + LN, accumulated into
+// h = U^(u0+u1 eps) F^(f0+f1 eps) exp(eps LN) = exp(X) exp(eps B) with
+// X = u0 log U + f0 log F and B = u1 log U + f1 log F + LN, accumulated into
 //   g = sum_Y prod_{j not in Y} 1/(b_j eps) prod_{j in Y} t_j^-1 t_j^(b_j eps) h^[Y],
 // index o of g holding order o - KS.
 template <int KS, int K, typename T>
@@ -216,42 +229,22 @@ __device__ __forceinline__ void mobius_series(const qmc_sec_dev *S, Point<KS, K,
     for (int Y = 0; Y < N; ++Y)
         P.bad |= !(mobius::corner<KS, T>(P.SU, Y) > T(0)) |
                  !(mobius::corner<KS, T>(P.SF, Y) > T(0));
-    T lU[N], lF[N], B[N], H[N];
-    mobius::log<KS, T>(P.SU, lU);
-    mobius::log<KS, T>(P.SF, lF);
+    T B[N], H[N];
+    {
+        T lU[N], lF[N], X[N];
+        mobius::log<KS, T>(P.SU, lU);
+        mobius::log<KS, T>(P.SF, lF);
 #pragma unroll
-    for (int Y = 0; Y < N; ++Y) B[Y] = fma(T(S->u1), lU[Y], T(S->f1) * lF[Y]);
-    B[0] += P.LN;
-    if (S->u0i != QMC_NO_INT && S->f0i != QMC_NO_INT) {
-        T pu[N], pf[N];
-        mobius::powi<KS, T>(P.SU, S->u0i, pu);
-        mobius::powi<KS, T>(P.SF, S->f0i, pf);
-        mobius::mul<KS, KS, T>(pu, pf, H);
-    } else {
-        T x[N];
-#pragma unroll
-        for (int Y = 0; Y < N; ++Y) x[Y] = fma(T(S->u0), lU[Y], T(S->f0) * lF[Y]);
-        mobius::exp<KS, T>(x, H);
-    }
-    T CY[N], LY[N];
-#pragma unroll
-    for (int Y = 0; Y < N; ++Y) {
-        T c = 1, L = 0;
-#pragma unroll
-        for (int j = 0; j < KS; ++j) {
-            if (Y >> j & 1) {
-                c *= P.invt[j];
-                L = fma(T(S->b[j]), P.lt[j], L);
-            } else {
-                c *= T(S->inv_b[j]);
-            }
+        for (int Y = 0; Y < N; ++Y) {
+            B[Y] = fma(T(S->u1), lU[Y], T(S->f1) * lF[Y]);
+            X[Y] = fma(T(S->u0), lU[Y], T(S->f0) * lF[Y]);
         }
-        CY[Y] = c;
-        LY[Y] = L;
+        B[0] += P.LN;
+        mobius::exp<KS, T>(X, H);
     }
 #pragma unroll
     for (int o = 0; o < K; ++o) g[o] = 0;
-    Accum<KS, K, 0, T>::run(B, H, CY, LY, g);
+    Accum<KS, K, 0, T>::run(S, P, B, H, g);
 }
 
 // ---- kernel -------------------------------------------------------------
@@ -320,7 +313,7 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                         constexpr int pole_lim = KS;
                         const bool pole = j < pole_lim;
                         const T bj = T(S->b[j]);
-                        lt[j] = log(t[j]);
+                        lt[j] = qmc_math::ln(t[j]);
                         if (pole) {
                             const int jp = pole ? j : 0;
                             P.invt[jp] = mobius::rcp(t[j]);
@@ -332,7 +325,7 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                                 P.E[jp][q] = P.E[jp][q - 1] * x * (T(1) / T(q));
                         } else {
                             LN = fma(bj, lt[j], LN);
-                            if (S->aint[j] == QMC_NO_INT) pn *= exp(T(S->a[j]) * lt[j]);
+                            if (S->aint[j] == QMC_NO_INT) pn *= qmc_math::ex(T(S->a[j]) * lt[j]);
                             else
                                 for (int k = 0; k < S->aint[j]; ++k) pn *= t[j];
                         }

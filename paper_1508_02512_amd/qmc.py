@@ -21,6 +21,7 @@ ERRORS = {-1: "QMC_EINVAL", -2: "QMC_EUNREGULATED", -3: "QMC_EUNSUPPORTED",
           -4: "QMC_ENOMEM", -5: "QMC_EBUDGET", -6: "QMC_EDEFORM",
           -7: "QMC_ENOTCONVERGED", -8: "QMC_EDEVICE", -9: "QMC_ECANCELLED"}
 QMC_FP64, QMC_FP32_EVAL = 0, 1
+QMC_MATH_LN, QMC_MATH_LN1P, QMC_MATH_EXP, QMC_MATH_EXPM1 = 0, 1, 2, 3
 QMC_MAX_DIM = 8
 
 P = C.POINTER
@@ -76,6 +77,12 @@ class qmc_tune_choice(C.Structure):
                 ("grid_per_cu", C.c_int32), ("ms", C.c_double)]
 
 
+class qmc_class_stat(C.Structure):
+    _fields_ = [("poles", C.c_int32), ("width", C.c_int32), ("points_per_lane", C.c_int32),
+                ("grid", C.c_int32), ("items", C.c_int32), ("precision", C.c_int32),
+                ("evals", C.c_uint64), ("algo_flops", C.c_double), ("ms", C.c_double)]
+
+
 class qmc_request(C.Structure):
     _fields_ = [("kin", P(C.c_double)), ("rel_err_target", C.c_double), ("n0", C.c_uint64),
                 ("n_max", C.c_uint64), ("m", C.c_int32), ("seed", C.c_uint64),
@@ -101,9 +108,13 @@ _SIGS = {
     "qmc_fetch": (C.c_int, [C.c_void_p, P(qmc_result)]),
     "qmc_job_free": (None, [C.c_void_p]),
     "qmc_job_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
+    "qmc_job_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
+    "qmc_job_class_stats": (C.c_int, [C.c_void_p, P(qmc_class_stat), C.c_int32,
+                                      P(C.c_int32)]),
     "qmc_autotune": (C.c_int, [C.c_void_p, C.c_void_p, P(C.c_double), C.c_int32,
                                P(qmc_lattice), P(qmc_lattice), P(C.c_double), C.c_int32,
                                P(qmc_tune_choice), C.c_int32, P(C.c_int32)]),
+    "qmc_math_eval": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64]),
     "qmc_submit": (C.c_int, [C.c_void_p, C.c_void_p, P(qmc_request), P(C.c_uint64)]),
     "qmc_poll": (C.c_int, [C.c_void_p, C.c_uint64, P(qmc_result)]),
     "qmc_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double, P(qmc_result)]),
@@ -159,6 +170,10 @@ class Context:
         if rc < 0:
             raise QMCError(rc, lib().qmc_last_error(self.h).decode())
         return rc
+
+    def math_eval(self, fn, x_ptr, y_ptr, n):
+        """The kernels' elementary function fn (QMC_MATH_*) on n device doubles."""
+        self.check(lib().qmc_math_eval(self.h, fn, C.c_void_p(x_ptr), C.c_void_p(y_ptr), n))
 
     def close(self):
         if self.h:
@@ -382,6 +397,20 @@ class Job:
 
     def use_graph(self, enable=True):
         self.plan.ctx.check(lib().qmc_job_set_graph(self.h, int(enable)))
+
+    def profile(self, enable=True):
+        """Time every kernel-class launch of later eager runs."""
+        self.plan.ctx.check(lib().qmc_job_set_profiling(self.h, int(enable)))
+
+    def class_stats(self):
+        """One dict per kernel launch of a run: class, shape, evaluations,
+        algorithmic flops and the launch time of the last fetched run."""
+        n = C.c_int32()
+        self.plan.ctx.check(lib().qmc_job_class_stats(self.h, None, 0, C.byref(n)))
+        arr = (qmc_class_stat * max(n.value, 1))()
+        self.plan.ctx.check(lib().qmc_job_class_stats(self.h, arr, n.value, C.byref(n)))
+        return [{f: getattr(arr[i], f) for f, _ in qmc_class_stat._fields_}
+                for i in range(n.value)]
 
     def fetch(self, sector_sums=False, per_shift=False):
         n_points, m = self.kin.shape[0], self.shifts.shape[0]

@@ -3,6 +3,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 from paper_1508_02512_amd import qmc
 
@@ -30,10 +31,31 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) <= set(qmc._SIGS)
 
 
-def test_binding_structs_match_header_sizes():
-    # sizes of the ABI structs on x86-64 (natural alignment)
-    assert ctypes.sizeof(qmc.qmc_poly) == 24
-    assert ctypes.sizeof(qmc.qmc_sector) == 8 + 16 + 48 + 32 + 16
-    assert ctypes.sizeof(qmc.qmc_lattice) == 16
-    assert ctypes.sizeof(qmc.qmc_coeff) == 32
-    assert ctypes.sizeof(qmc.qmc_result) == 24 + 16 + 8 + 16 + 16
+STRUCTS = ("qmc_poly", "qmc_sector", "qmc_problem", "qmc_plan_opts", "qmc_lattice",
+           "qmc_coeff", "qmc_plan_info", "qmc_result", "qmc_tune_choice", "qmc_class_stat",
+           "qmc_request")
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every ctypes struct has the size and field offsets that a C compiler
+    gives the header's struct of the same name."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qmc.h"',
+             "int main(void) {"]
+    for name in STRUCTS:
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in getattr(qmc, name)._fields_:
+            # a trailing underscore marks a C field named like a Python keyword
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f.rstrip("_")}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.splitlines())
+    for name in STRUCTS:
+        T = getattr(qmc, name)
+        assert int(got[name]) == ctypes.sizeof(T), name
+        for f, _ in T._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(T, f).offset, f"{name}.{f}"

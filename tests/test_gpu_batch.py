@@ -33,7 +33,7 @@ def _inputs(plan, info, svals):
 
 def test_batch_parity_graph_and_grid():
     print("batch: triangle2l 24 points, uneven lattices", flush=True)
-    plan, info = gpu_plan("triangle2l", lam=0.5)
+    plan, info = gpu_plan("triangle2l", lam=0.25)
     svals = _batch()
     kin, lats = _inputs(plan, info, svals)
     sh = shift_table(5, 3, 8)
@@ -56,7 +56,7 @@ def test_batch_parity_graph_and_grid():
         for s in rng.choice(len(osecs), size=4, replace=False):
             ns = oq.NumericSector(osecs[s], oinfo, {"s": float(svals[p]), "msq": 1.0})
             n, z = lats[s]
-            sums, abss, _ = oq.sector_sums(ns, n, z, sh, 2, oq.effective_lambda(ns, 0.5),
+            sums, abss, _ = oq.sector_sums(ns, n, z, sh, 2, oq.effective_lambda(ns, 0.25),
                                            eager["sec_lo"], plan.info.sec_orders)
             scale = abss[..., 0] + abss[..., 1]
             err = np.abs(eager["sector_sums"][p, s] - sums)
@@ -66,7 +66,7 @@ def test_batch_parity_graph_and_grid():
 
 def test_autotune_then_same_result():
     print("batch: autotune", flush=True)
-    plan, info = gpu_plan("triangle2l", lam=0.5)
+    plan, info = gpu_plan("triangle2l", lam=0.25)
     svals = _batch(8, seed=3)
     kin, lats = _inputs(plan, info, svals)
     sh = shift_table(6, 2, 8)
@@ -77,3 +77,29 @@ def test_autotune_then_same_result():
     b, a = before["sector_sums"], after["sector_sums"]
     assert np.allclose(a, b, rtol=1e-12, atol=1e-13 * np.max(np.abs(b)))
     plan.close()
+
+
+def test_class_stats_account_for_the_whole_run():
+    print("batch: per-class launch stats", flush=True)
+    plan, info = gpu_plan("triangle2l", lam=0.25)
+    svals = np.array([-5.0, -1.0, 2.0, 5.0, 7.0, -8.0, 9.0, 4.5])
+    kin, lats = _inputs(plan, info, svals)
+    sh = shift_table(2, 3, 8)
+    job = plan.bind(kin, None, sh, lat_per_sector=lats)
+    job.profile(True)
+    job.run()
+    res = job.fetch()
+    st = job.class_stats()
+    assert len(st) >= 2                      # real and deformed sectors both occur
+    assert sum(c["evals"] for c in st) == res["evals"]
+    assert np.isclose(sum(c["algo_flops"] for c in st), res["algo_flops"], rtol=1e-12)
+    assert all(c["ms"] > 0 and c["grid"] >= 1 and c["items"] >= c["grid"] for c in st)
+    assert sum(c["ms"] for c in st) <= res["kernel_ms"] * 1.01 + 0.05
+    keys = [(c["poles"], c["width"]) for c in st]
+    assert keys == sorted(keys) and len(set(keys)) == len(keys)
+    # graph replay records no per-class events
+    job.use_graph(True)
+    job.run()
+    job.fetch()
+    assert all(c["ms"] == -1.0 for c in job.class_stats())
+    job.close()

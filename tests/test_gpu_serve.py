@@ -22,8 +22,11 @@ def test_single_request_converges_and_matches_integrate():
     print("serve: one box request", flush=True)
     plan, info = gpu_plan("box")
     kin = _box_kin(info)
-    r = qmc.submit(plan, kin, 1e-6, 1 << 12, 1 << 22, 8, 7, Z).wait(120)
-    assert r["rc"] == 0 and r["steps"] >= 2
+    # the box reaches 1e-6 on the first 2^12 points; a tighter target makes
+    # the request double its lattice several times before it retires
+    r = qmc.submit(plan, kin, 1e-10, 1 << 10, 1 << 22, 8, 7, Z).wait(120)
+    assert r["rc"] == 0 and r["steps"] >= 3
+    assert r["n_final"] == (1 << 10) << (r["steps"] - 1)
     # the doubled lattice reproduces one pass over the same 2^k points
     ref = plan.integrate(kin, (r["n_final"], Z), shift_table(7, 8, 8))
     assert np.allclose(r["mean"], ref["mean"], rtol=1e-12, atol=1e-14)
