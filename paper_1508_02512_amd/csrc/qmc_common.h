@@ -7,6 +7,37 @@
 
 namespace qmc {
 
+// Inputs that no kernel writes (sector headers, lattices, term tables,
+// shifts, work items) are read through the constant address space: the
+// compiler may then fetch wave-uniform values with scalar loads into SGPRs
+// instead of vector loads into VGPRs, which it must otherwise assume the
+// kernel's own stores could alias.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> ro(const T *p)
+{
+    return (cptr<T>)p;
+}
+
+// one work item, field by field (a struct copy out of the constant address
+// space is not expressible)
+__device__ __forceinline__ qmc_item load_item(const qmc_item *items, int i)
+{
+    cptr<qmc_item> p = ro(items) + i;
+    qmc_item it;
+    it.sector = p->sector;
+    it.point = p->point;
+    it.shift = p->shift;
+    it.group = p->group;
+    it.lat = p->lat;
+    it.start = p->start;
+    it.count = p->count;
+    it.stride = p->stride;
+    return it;
+}
+
 // ---------------------------------------------------------------- helpers
 
 __device__ __forceinline__ void neumaier(double &s, double &c, double x)

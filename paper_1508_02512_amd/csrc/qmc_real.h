@@ -50,7 +50,7 @@ __device__ __forceinline__ T tmono(uint32_t e, const T *t, const T *t2, const T 
 // prod_j t_j^e_j = exp(sum_j e_j ln t_j): branch-free for wave-uniform
 // exponents (t_j > 0 wherever the real kernel evaluates a monomial)
 template <typename T>
-__device__ __forceinline__ T tmono_log(const double *e, const T *lt, int d)
+__device__ __forceinline__ T tmono_log(cptr<double> e, const T *lt, int d)
 {
     T x = 0;
 #pragma unroll
@@ -109,7 +109,7 @@ struct Point {
 // ---- corner path (few poles) -------------------------------------------
 
 template <int KS, int K, typename T>
-__device__ __forceinline__ void leaf(const qmc_sec_dev *S, Point<KS, K, T> &P, int X, T (&h)[K])
+__device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, Point<KS, K, T> &P, int X, T (&h)[K])
 {
     constexpr int full = (1 << KS) - 1;
     const T u = P.SU[full ^ X];
@@ -147,7 +147,7 @@ __device__ __forceinline__ void fold(T (&A)[K], const T (&B)[K], T invb, T invt,
 
 template <int LEVEL, int XB, int KS, int K, typename T>
 struct Tree {
-    static __device__ __forceinline__ void run(const qmc_sec_dev *S, Point<KS, K, T> &P,
+    static __device__ __forceinline__ void run(cptr<qmc_sec_dev> S, Point<KS, K, T> &P,
                                                T (&out)[K])
     {
         T B[K];
@@ -159,7 +159,7 @@ struct Tree {
 
 template <int XB, int KS, int K, typename T>
 struct Tree<0, XB, KS, K, T> {
-    static __device__ __forceinline__ void run(const qmc_sec_dev *S, Point<KS, K, T> &P,
+    static __device__ __forceinline__ void run(cptr<qmc_sec_dev> S, Point<KS, K, T> &P,
                                                T (&out)[K])
     {
         leaf<KS, K, T>(S, P, XB, out);
@@ -174,7 +174,7 @@ struct Tree<0, XB, KS, K, T> {
 // L(Y) = sum_{j in Y} b_j ln t_j (formed where used: fewer live registers).
 template <int KS, int K, int Q, typename T>
 struct Accum {
-    static __device__ __forceinline__ void run(const qmc_sec_dev *S, const Point<KS, K, T> &P,
+    static __device__ __forceinline__ void run(cptr<qmc_sec_dev> S, const Point<KS, K, T> &P,
                                                const T (&B)[1 << KS], T (&H)[1 << KS],
                                                T (&g)[K])
     {
@@ -221,7 +221,7 @@ struct Accum {
 //   g = sum_Y prod_{j not in Y} 1/(b_j eps) prod_{j in Y} t_j^-1 t_j^(b_j eps) h^[Y],
 // index o of g holding order o - KS.
 template <int KS, int K, typename T>
-__device__ __forceinline__ void mobius_series(const qmc_sec_dev *S, Point<KS, K, T> &P,
+__device__ __forceinline__ void mobius_series(cptr<qmc_sec_dev> S, Point<KS, K, T> &P,
                                               T (&g)[K])
 {
     constexpr int N = 1 << KS;
@@ -253,14 +253,15 @@ __device__ __forceinline__ void mobius_series(const qmc_sec_dev *S, Point<KS, K,
 template <int KS, int K, typename T>
 __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, const int item_id)
 {
-    const qmc_item it = A.items[item_id];
-    const qmc_sec_dev *S = A.sec + it.sector;
-    const qmc_lat_dev *L = A.lat + it.lat;
+    const qmc_item it = load_item(A.items, item_id);
+    cptr<qmc_sec_dev> S = ro(A.sec) + it.sector;
+    cptr<qmc_lat_dev> L = ro(A.lat) + it.lat;
     const int d = S->dim;
     const uint32_t n = L->n;
     const double inv_n = L->inv_n;
-    const double *coef = A.tcoef + (size_t)it.point * A.n_terms;
-    const double *shift = A.shifts + it.shift * QMC_DMAX;
+    cptr<double> coef = ro(A.tcoef) + (size_t)it.point * A.n_terms;
+    cptr<double> shift = ro(A.shifts) + it.shift * QMC_DMAX;
+    cptr<double> texpd = ro(A.texpd);
     const int r = A.korobov_r;
 
     uint32_t l[QMC_DMAX], step[QMC_DMAX];
@@ -337,9 +338,9 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                 for (int m = 0; m < (1 << KS); ++m) {
                     T su = 0, sf = 0;
                     for (int q = S->um[m]; q < S->um[m + 1]; ++q)
-                        su = fma(T(coef[q]), tmono_log<T>(A.texpd + q * QMC_DMAX, lt, d), su);
+                        su = fma(T(coef[q]), tmono_log<T>(texpd + q * QMC_DMAX, lt, d), su);
                     for (int q = S->fm[m]; q < S->fm[m + 1]; ++q)
-                        sf = fma(T(coef[q]), tmono_log<T>(A.texpd + q * QMC_DMAX, lt, d), sf);
+                        sf = fma(T(coef[q]), tmono_log<T>(texpd + q * QMC_DMAX, lt, d), sf);
                     P.SU[m] = su;
                     P.SF[m] = sf;
                 }
@@ -385,8 +386,19 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
 // per work-group when the grid covers the list, a persistent loop when the
 // grid is smaller.  Each item writes only its own slot, so the result does
 // not depend on the grid.
+// Minimum waves per SIMD the register allocator must allow (measured on
+// the planar double box; more occupancy spills instead): two for three
+// poles, and for four poles in FP32; the other classes reach three or more
+// by themselves, the FP64 four-pole class runs fastest at one.
+template <int KS, typename T>
+constexpr int min_waves()
+{
+    return KS == 3 || (KS == 4 && sizeof(T) == 4) ? 2 : 1;
+}
+
 template <int KS, int K, typename T>
-__global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_real(qmc_launch_args A)
+__global__ __launch_bounds__(QMC_BLOCK)
+__attribute__((amdgpu_waves_per_eu(min_waves<KS, T>(), 8))) void qmc_eval_real(qmc_launch_args A)
 {
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
         qmc_eval_real_item<KS, K, T>(A, item);
