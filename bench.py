@@ -29,6 +29,14 @@ DOUBLING_PRIMES = [65521, 131071, 262139, 524287, 1048573, 2097143, 4194301,
                    8388593, 16777213, 33554393, 67108859]
 
 
+# HBM bytes (read + written) per launch of the integrand kernel for a
+# (poles, complex width, n, m) class of this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes calibrated with a 256 MiB copy (recorded
+# in profiles/qmc_eval_real_doublebox_n1000003_counters.md).  A class absent
+# here was not measured with the current kernel and reports null.
+TRAFFIC_BYTES = {(4, 0, 1000003, 16): 14.85e6, (3, 0, 1000003, 16): 37.24e6}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,7 +373,8 @@ def main():
                    "sectors": plan.n_sectors, "lattice_n": n, "shifts": m,
                    "evals_per_step": evals_per_step, "precision": "fp64"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                     "traffic": TRAFFIC_BYTES.get((dom_stat["poles"], dom_stat["width"], n, m)),
                      "kernel": f"qmc_eval_real<poles={dom_stat['poles']}, double>"
                                if dom_stat["width"] == 0 else
                                f"qmc_eval_cplx<width={dom_stat['width']}, "
