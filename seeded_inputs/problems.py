@@ -157,8 +157,45 @@ DOUBLEBOX_OFF14 = _doublebox_legs((1, 4))
 DOUBLEBOX_OFF24 = _doublebox_legs((2, 4))
 DOUBLEBOX_OFF34 = _doublebox_legs((3, 4))
 
+# Higgs-pair kinematics of Section IV.C-D: incoming gluons p1, p2
+# (p1^2 = p2^2 = 0), outgoing Higgs bosons p3, p4 (p^2 = mhsq),
+# p4 = p1 + p2 - p3, s = (p1+p2)^2, t = (p2-p3)^2, so
+# p2.p3 = (mhsq - t)/2 and p1.p3 = (s + t - mhsq)/2.
+_SP_HH = {
+    ("p1", "p1"): {}, ("p2", "p2"): {}, ("p3", "p3"): {"mhsq": "1"},
+    ("p1", "p2"): {"s": "1/2"},
+    ("p2", "p3"): {"mhsq": "1/2", "t": "-1/2"},
+    ("p1", "p3"): {"s": "1/2", "t": "1/2", "mhsq": "-1/2"},
+}
+
+# I_C (Section IV.C): planar double box with four top-quark lines,
+# k1^2, (k1-p1)^2, (k1+p2)^2, (k1-k2-p1)^2-mt^2, k2^2-mt^2,
+# (k1+p2-k2-p3)^2-mt^2, (k1-k2+p2)^2-mt^2.
+HH_PLANAR = Problem(
+    "hh_planar", 2, ("p1", "p2", "p3"), ("s", "t", "mtsq", "mhsq"), _SP_HH,
+    (_P([1, 0]), _P([1, 0], {"p1": -1}), _P([1, 0], {"p2": 1}),
+     _P([1, -1], {"p1": -1}, mass="mtsq"), _P([0, 1], mass="mtsq"),
+     _P([1, -1], {"p2": 1, "p3": -1}, mass="mtsq"),
+     _P([1, -1], {"p2": 1}, mass="mtsq")),
+    note="planar two-loop double box for gg -> HH (Section IV.C, Table 2)")
+
+# I_D (Section IV.D): non-planar double box with four top-quark lines,
+# k1^2, (k1+p1)^2, (k1-p2)^2, (k1+p1-k2)^2-mt^2, k2^2-mt^2,
+# (k2-p4)^2-mt^2, (k1+p1-k2-p3)^2-mt^2.
+HH_NONPLANAR = Problem(
+    "hh_nonplanar", 2, ("p1", "p2", "p3"), ("s", "t", "mtsq", "mhsq"), _SP_HH,
+    (_P([1, 0]), _P([1, 0], {"p1": 1}), _P([1, 0], {"p2": -1}),
+     _P([1, -1], {"p1": 1}, mass="mtsq"), _P([0, 1], mass="mtsq"),
+     _P([0, 1], {"p1": -1, "p2": -1, "p3": 1}, mass="mtsq"),
+     _P([1, -1], {"p1": 1, "p3": -1}, mass="mtsq")),
+    note="non-planar two-loop double box for gg -> HH (Section IV.D, Table 3)")
+
+# The kinematic point of Tables 2 and 3 (GeV^2): s = 160000, t = -6000,
+# M_t = 172, M_H = 125 (Section IV).
+HH_POINT = {"s": 160000.0, "t": -6000.0, "mtsq": 172.0 ** 2, "mhsq": 125.0 ** 2}
+
 PROBLEMS = {p.name: p for p in (BUBBLE, BUBBLE_MASSIVE, BOX, TRIANGLE_OFFSHELL,
                                 DOUBLEBOX,
                                 DOUBLEBOX_OFFSHELL, DOUBLEBOX_OFF14,
                                 DOUBLEBOX_OFF24, DOUBLEBOX_OFF34,
-                                NP_VERTEX, TRIANGLE2L)}
+                                NP_VERTEX, TRIANGLE2L, HH_PLANAR, HH_NONPLANAR)}

@@ -84,3 +84,16 @@ def test_triangle2l(s):
     print(f"triangle2l s={s}", flush=True)
     res, _ = compare_sectors("triangle2l", {"s": s, "msq": 1.0}, 1009, 2, lam=0.5)
     assert res["violations"] == 0
+
+
+@pytest.mark.parametrize("name,lam", [("hh_planar", 1.0), ("hh_nonplanar", 0.5)])
+def test_hh_double_boxes_sectors(name, lam):
+    """The gg -> HH double boxes of Section IV.C-D at the Table 2-3 point:
+    deformed six-dimensional sectors, sampled per pole count, against the
+    oracle sector by sector."""
+    from gpu_util import sample_sectors
+    from seeded_inputs.problems import HH_POINT
+    print(f"{name} sectors lambda={lam}", flush=True)
+    res, _ = compare_sectors(name, HH_POINT, 1009, 2, lam=lam,
+                             sectors=sample_sectors(name, per_class=6))
+    assert res["violations"] == 0
