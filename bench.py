@@ -52,7 +52,7 @@ def parse():
                     help="also run the non-planar vertex and the 512-point batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM counters)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=0.25)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
@@ -88,22 +88,42 @@ def cpu_baseline(target_seconds):
                       f"n={n}, m={m} shifts, FP64 oracle, {cores} threads"}
 
 
+# masses of Section IV (GeV^2) for the physical two-loop planar box I_C
+MT2, MH2 = 172.0 ** 2, 125.0 ** 2
+
+
+def serve_kinematics(rng, kind):
+    """Seeded physical kinematics of one serving request."""
+    if kind == 2:
+        return "np_vertex", {"s": float(rng.uniform(4.2, 8.0)), "msq": 1.0}
+    if kind == 0:
+        sv = float(rng.uniform(1.0, 10.0))
+        return "box", {"s": sv, "t": float(rng.uniform(-sv + 0.1, -0.1))}
+    # gg -> HH above the top-pair threshold: s in [1.3e5, 2.5e5] GeV^2,
+    # scattering angle cos(theta) in [-0.8, 0.8]
+    sv = float(rng.uniform(1.3e5, 2.5e5))
+    beta = (1.0 - 4.0 * MH2 / sv) ** 0.5
+    t = MH2 - 0.5 * sv * (1.0 - beta * float(rng.uniform(-0.8, 0.8)))
+    return "hh_planar", {"s": sv, "t": t, "mtsq": MT2, "mhsq": MH2}
+
+
 def serve_bench(qmc, fe, PROBLEMS, lattice, seconds, rate, fp32, slots, log):
     """Poisson request stream (seeded) mixing the one-loop box, the planar
-    double box and the non-planar vertex at physical kinematics, target
-    1e-3 relative; embedded lattices n = 2^14 .. 2^22 doubling, 8 shifts."""
+    two-loop box of Section IV.C (I_C) and the non-planar vertex, all at
+    physical kinematics, target 1e-3 relative; embedded lattices
+    n = 2^14 .. 2^22 doubling, 8 shifts, up to 4 deformation back-offs."""
     import numpy as np
 
     rng = np.random.default_rng(0)
     prec = qmc.QMC_FP32_EVAL if fp32 else qmc.QMC_FP64
     ctx = qmc.Context(0, max_slots=slots)
     plans = {}
-    for name, lam in (("box", 0.5), ("doublebox", 0.25), ("np_vertex", 0.5)):
+    for name, lam in (("box", 0.5), ("hh_planar", 1.0), ("np_vertex", 0.5)):
         secs, info = fe.decompose(PROBLEMS[name])
         plans[name] = (ctx.plan(fe.sector_arrays(secs, info), info, 0,
                                 fe.prefactor_series(info, 12), lam=lam, precision=prec), info)
     z = lattice(1 << 24)
-    n_req = int(seconds * rate)
+    n_req = max(int(seconds * rate), 1)
     gaps = rng.exponential(1.0 / rate, size=n_req)
     kinds = rng.integers(0, 3, size=n_req)
     reqs = []
@@ -113,25 +133,26 @@ def serve_bench(qmc, fe, PROBLEMS, lattice, seconds, rate, fp32, slots, log):
         t_next += gaps[i]
         while time.perf_counter() < t_next:
             time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
-        if kinds[i] == 2:
-            name = "np_vertex"
-            vals = {"s": float(rng.uniform(4.2, 8.0)), "msq": 1.0}
-        else:
-            name = "box" if kinds[i] == 0 else "doublebox"
-            sv = float(rng.uniform(1.0, 10.0))
-            vals = {"s": sv, "t": float(rng.uniform(-sv + 0.1, -0.1))}
+        name, vals = serve_kinematics(rng, int(kinds[i]))
         plan, info = plans[name]
         reqs.append((name, qmc.submit(plan, fe.kin_vector(info, vals), 1e-3, 1 << 14, 1 << 22,
-                                      8, 1000 + i, z)))
+                                      8, 1000 + i, z, lambda_halvings=4)))
     lat, evals, status = [], 0, {}
+    per = {}
     for name, r in reqs:
-        out = r.wait(600)
+        out = r.wait(900)
         if out is None:
             status["timeout"] = status.get("timeout", 0) + 1
             continue
         lat.append(out["latency_ms"])
         evals += out["evals"]
         status[out["rc"]] = status.get(out["rc"], 0) + 1
+        d = per.setdefault(name, {"n": 0, "ok": 0, "latency_ms": [], "n_final": [], "halv": 0})
+        d["n"] += 1
+        d["ok"] += out["rc"] == 0
+        d["halv"] += out["lambda_halvings"]
+        d["latency_ms"].append(out["latency_ms"])
+        d["n_final"].append(out["n_final"])
         r.release()
     wall = time.perf_counter() - t0
     for plan, _ in plans.values():
@@ -143,9 +164,14 @@ def serve_bench(qmc, fe, PROBLEMS, lattice, seconds, rate, fp32, slots, log):
            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
            "completed_req_s": len(lat) / wall, "evals_per_s": evals / wall,
-           "wall_s": wall, "status_counts": {str(k): v for k, v in status.items()}}
+           "wall_s": wall, "status_counts": {str(k): v for k, v in status.items()},
+           "per_problem": {k: {"requests": v["n"], "converged": v["ok"],
+                               "p50_ms": float(np.percentile(v["latency_ms"], 50)),
+                               "median_n_final": int(np.median(v["n_final"])),
+                               "lambda_halvings": v["halv"]}
+                           for k, v in per.items()}}
     log(f"serve ({res['precision']}, slots {slots}): p50 {res['p50_ms']} ms, "
-        f"p99 {res['p99_ms']} ms, {res['completed_req_s']:.1f} req/s")
+        f"p99 {res['p99_ms']} ms, {res['completed_req_s']:.1f} req/s, {res['per_problem']}")
     return res
 
 

@@ -141,7 +141,7 @@ typedef struct {
     double algo_flops;           /* algorithmic flops of the integrand kernels */
     double latency_ms;           /* serving: submit to completion (0 for qmc_integrate) */
     int32_t steps;               /* serving: lattice sizes evaluated (doublings + 1) */
-    int32_t reserved;
+    int32_t lambda_halvings;     /* serving: deformation back-offs taken (see qmc_request) */
 } qmc_result;
 
 /* Create a context on `device` with at most hbm_budget bytes of device
@@ -255,7 +255,14 @@ int qmc_math_eval(qmc_ctx *ctx, int32_t fn, const double *x, double *y, int64_t 
  * checked against the target, and the request completes when every order
  * has err/|mean| <= target (orders below 1e-3 of the largest are compared
  * absolutely against the largest), when n_max is reached
- * (QMC_ENOTCONVERGED), or when it is cancelled.  A request's arithmetic does
+ * (QMC_ENOTCONVERGED), or when it is cancelled.  If a batch finds points
+ * where the deformed contour violates the sign conditions (Im F(z) > 0 or
+ * Re U(z) <= 0; Eq. 14 guarantees them only for small enough lambda), the
+ * request retires with QMC_EDEFORM unless it still has back-offs
+ * (lambda_halvings): then lambda is halved in the sectors that violated
+ * and the request restarts at n0 with its sums cleared.  A sector's
+ * integral does not depend on the contour (Cauchy), so only its variance
+ * changes.  A request's arithmetic does
  * not depend on the other requests in the batch, so its result is the
  * same alone and in the mix. */
 typedef struct {
@@ -265,6 +272,8 @@ typedef struct {
     int32_t m;                   /* shifts (>= 2) */
     uint64_t seed;               /* SplitMix64 seed of the shifts (k-major, 53-bit) */
     const uint32_t *z;           /* [QMC_MAX_DIM] odd generating vector */
+    int32_t lambda_halvings;     /* deformed sectors: back-offs allowed (0..16), see below */
+    int32_t pad;
 } qmc_request;
 
 /* Queue a request; returns a ticket.  Thread-safe; returns immediately. */

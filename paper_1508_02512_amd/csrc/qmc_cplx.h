@@ -16,6 +16,7 @@
 #include "qmc_common.h"
 #include "qmc_device.h"
 #include "qmc_kernels.h"
+#include "qmc_math.h"
 
 namespace qmc_cplx {
 
@@ -36,7 +37,7 @@ __device__ __forceinline__ cd cscale(cd a, double s) { return {a.r * s, a.i * s}
 
 __device__ __forceinline__ cd crecip(cd a)
 {
-    const double inv = 1.0 / fma(a.r, a.r, a.i * a.i);
+    const double inv = qmc_math::rcp(fma(a.r, a.r, a.i * a.i));
     return {a.r * inv, -a.i * inv};
 }
 
@@ -51,7 +52,7 @@ __device__ __forceinline__ cd cpowi(cd x, int e)
 // principal logarithm; a real negative argument takes -i pi (the -i0 side)
 __device__ __forceinline__ cd clog_m(cd x)
 {
-    const double m = 0.5 * log(fma(x.r, x.r, x.i * x.i));
+    const double m = 0.5 * qmc_math::ln(fma(x.r, x.r, x.i * x.i));
     double a = atan2(x.i, x.r);
     if (x.i == 0.0 && x.r < 0.0) a = -M_PI;
     return {m, a};
@@ -59,7 +60,7 @@ __device__ __forceinline__ cd clog_m(cd x)
 
 __device__ __forceinline__ cd cexp_(cd x)
 {
-    const double e = exp(x.r);
+    const double e = qmc_math::ex(x.r);
     double s, c;
     sincos(x.i, &s, &c);
     return {e * c, e * s};
@@ -118,16 +119,16 @@ struct CplxPoint {
     double invt[KS > 0 ? KS : 1];
     double E[KS > 0 ? KS : 1][K];   // (b_j ln t_j)^r / r! of the pole variables
     double LN;                       // sum_{j >= ks} b_j ln t_j
-    const double *coef;              // U, F coefficients at this point
-    const double *dcoef;             // derivative coefficients at this point
-    const uint32_t *texp, *dexp;
+    cptr<double> coef;               // U, F coefficients at this point
+    cptr<double> dcoef;              // derivative coefficients at this point
+    cptr<uint32_t> texp, dexp;
     double lam;                      // deformation parameter of this sector and point
     int bad;
 };
 
 // h at corner X (pole variables in X set to 0), deformed, as a series
 template <int DM, int KS, int K>
-__device__ __forceinline__ void leaf(const qmc_sec_dev *S, CplxPoint<DM, KS, K> &P, int X,
+__device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &P, int X,
                                      cd (&h)[K])
 {
     double tp[DM], op[DM], tp2[DM], tp3[DM];
@@ -230,7 +231,7 @@ __device__ __forceinline__ void leaf(const qmc_sec_dev *S, CplxPoint<DM, KS, K> 
     for (int j = 0; j < DM; ++j) {
         if (j >= d || qv[j] == 0.0) continue;
         // Log phi_j = 1/2 log(1 + q^2) - i atan(q)
-        const cd lphi = {0.5 * log1p(qv[j] * qv[j]), -atan(qv[j])};
+        const cd lphi = {0.5 * qmc_math::ln1p(qv[j] * qv[j]), -atan(qv[j])};
         L = cadd(L, cscale(lphi, S->b[j]));
         const int ai = j < KS ? -1 : S->aint[j];
         if (ai == QMC_NO_INT)
@@ -266,7 +267,7 @@ __device__ __forceinline__ void cfold(cd (&A)[K], const cd (&B)[K], double invb,
 // large, so it is instantiated once); partial folds wait on a stack whose
 // levels are unrolled: corner X completes level l when bit l of X is set.
 template <int DM, int KS, int K>
-__device__ __forceinline__ void corners_folded(const qmc_sec_dev *S, CplxPoint<DM, KS, K> &P,
+__device__ __forceinline__ void corners_folded(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &P,
                                                cd (&out)[K])
 {
     cd stack[KS > 0 ? KS : 1][K];
@@ -301,13 +302,13 @@ __device__ __forceinline__ void corners_folded(const qmc_sec_dev *S, CplxPoint<D
 template <int DM, int KS, int K>
 __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, const int item_id)
 {
-    const qmc_item it = A.items[item_id];
-    const qmc_sec_dev *S = A.sec + it.sector;
-    const qmc_lat_dev *L = A.lat + it.lat;
+    const qmc_item it = load_item(A.items, item_id);
+    cptr<qmc_sec_dev> S = ro(A.sec) + it.sector;
+    cptr<qmc_lat_dev> L = ro(A.lat) + it.lat;
     const int d = S->dim;
     const uint32_t n = L->n;
     const double inv_n = L->inv_n;
-    const double *shift = A.shifts + it.shift * QMC_DMAX;
+    cptr<double> shift = ro(A.shifts) + it.shift * QMC_DMAX;
     const int r = A.korobov_r;
 
     uint32_t l[DM], step[DM];
@@ -334,11 +335,11 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
         const uint32_t off = threadIdx.x + (uint32_t)p * QMC_BLOCK;
         if (off < it.count) {
             CplxPoint<DM, KS, K> P;
-            P.coef = A.tcoef + (size_t)it.point * A.n_terms;
-            P.dcoef = A.dcoef + (size_t)it.point * A.n_dterms;
-            P.texp = A.texp;
-            P.dexp = A.dexp;
-            P.lam = A.lam[(size_t)it.point * A.n_sec + it.sector];
+            P.coef = ro(A.tcoef) + (size_t)it.point * A.n_terms;
+            P.dcoef = ro(A.dcoef) + (size_t)it.point * A.n_dterms;
+            P.texp = ro(A.texp);
+            P.dexp = ro(A.dexp);
+            P.lam = ro(A.lam)[(size_t)it.point * A.n_sec + it.sector];
             P.bad = 0;
             double w = 1.0;
             bool skip = false;
@@ -362,11 +363,11 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
                     P.lt[j] = 0.0;
                     if (j < d) {
                         const bool pole = j < KS;
-                        const double lt = log(P.t[j]);
+                        const double lt = qmc_math::ln(P.t[j]);
                         P.lt[j] = lt;
                         const double bj = S->b[j];
                         if (pole) {
-                            P.invt[pole ? j : 0] = 1.0 / P.t[j];
+                            P.invt[pole ? j : 0] = qmc_math::rcp(P.t[j]);
                             const double x = bj * lt;
                             P.E[pole ? j : 0][0] = 1.0;
 #pragma unroll
@@ -374,7 +375,7 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
                                 P.E[pole ? j : 0][q] = P.E[pole ? j : 0][q - 1] * x * (1.0 / q);
                         } else {
                             LN = fma(bj, lt, LN);
-                            if (S->aint[j] == QMC_NO_INT) pn *= exp(S->a[j] * lt);
+                            if (S->aint[j] == QMC_NO_INT) pn *= qmc_math::ex(S->a[j] * lt);
                             else
                                 for (int k = 0; k < S->aint[j]; ++k) pn *= P.t[j];
                         }

@@ -48,6 +48,7 @@ struct Request {
     uint64_t evals = 0;
     long violations = 0;
     int steps = 0;
+    int halvings_left = 0, halvings = 0; // deformation back-offs (allowed, taken)
     int status = QMC_PENDING;
     bool cancelled = false, done = false;
     clk::time_point t_submit, t_done;
@@ -136,6 +137,7 @@ void finish(qmc_serve_state *S, Request *r, int status)
 
 bool converged(const Request *r)
 {
+    if (r->n_cur == 0) return false;         // restarted: no result yet
     double maxs = 0.0;
     for (const qmc_coeff &c : r->coeff) maxs = std::max(maxs, std::hypot(c.re, c.im));
     for (const qmc_coeff &c : r->coeff) {
@@ -335,10 +337,31 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act)
     for (Request *r : act) {
         const qmc_plan *P = r->plan;
         const int ns = (int)P->secs.size();
+        r->evals += r->step_count * (uint64_t)ns * r->m;
+        r->steps += 1;
+        // sign violations of the deformed contour: back off lambda in the
+        // sectors concerned and restart the request while back-offs remain
+        std::vector<long> vsec(ns, 0);
+        long vtot = 0;
+        for (int s = 0; s < ns; ++s)
+            for (int k = 0; k < r->m; ++k) {
+                vsec[s] += gviol[r->group_base + s * r->m + k];
+                vtot += gviol[r->group_base + s * r->m + k];
+            }
+        if (vtot > 0 && r->halvings_left > 0) {
+            for (int s = 0; s < ns; ++s)
+                if (vsec[s] > 0) r->lam[s] *= 0.5;
+            r->halvings_left -= 1;
+            r->halvings += 1;
+            std::fill(r->hi.begin(), r->hi.end(), 0.0);
+            std::fill(r->lo.begin(), r->lo.end(), 0.0);
+            r->n_cur = 0;                    // the next step starts again at n0
+            continue;
+        }
+        r->violations += vtot;
         for (int s = 0; s < ns; ++s)
             for (int k = 0; k < r->m; ++k) {
                 const int g = r->group_base + s * r->m + k;
-                r->violations += gviol[g];
                 for (int q = 0; q < P->kstride * 2; ++q) {
                     const size_t o = ((size_t)(s * r->m + k) * P->kstride * 2) + q;
                     const double x = out[(size_t)g * kstride * 2 + q];
@@ -348,8 +371,6 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act)
                 }
             }
         r->n_cur = r->step_n;
-        r->steps += 1;
-        r->evals += r->step_count * (uint64_t)ns * r->m;
         std::vector<double> gsum(r->hi.size());
         for (size_t i = 0; i < gsum.size(); ++i) gsum[i] = r->hi[i] + r->lo[i];
         std::vector<uint64_t> nsec(ns, r->n_cur);
@@ -468,6 +489,7 @@ void fill(const Request *r, qmc_result *out)
     out->latency_ms =
         std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
     out->steps = r->steps;
+    out->lambda_halvings = r->halvings;
 }
 
 } // namespace
@@ -501,6 +523,8 @@ extern "C" int qmc_submit(qmc_ctx *ctx, const qmc_plan *plan, const qmc_request 
         return qmc_set_error(ctx, QMC_EINVAL, "n0 <= n_max must be powers of two below 2^31");
     if (!(req->rel_err_target > 0.0))
         return qmc_set_error(ctx, QMC_EINVAL, "rel_err_target must be positive");
+    if (req->lambda_halvings < 0 || req->lambda_halvings > 16)
+        return qmc_set_error(ctx, QMC_EINVAL, "lambda_halvings must be in 0..16");
     for (int j = 0; j < QMC_DMAX; ++j)
         if ((req->z[j] & 1u) == 0u)
             return qmc_set_error(ctx, QMC_EINVAL, "z must be odd (coprime to 2^k)");
@@ -514,6 +538,7 @@ extern "C" int qmc_submit(qmc_ctx *ctx, const qmc_plan *plan, const qmc_request 
     r->n0 = req->n0;
     r->n_max = req->n_max;
     r->m = req->m;
+    r->halvings_left = req->lambda_halvings;
     std::memcpy(r->z, req->z, sizeof r->z);
     splitmix_shifts(req->seed, r->m, r->shifts);
     const int ns = (int)plan->secs.size();

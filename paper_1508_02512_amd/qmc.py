@@ -69,7 +69,7 @@ class qmc_result(C.Structure):
                 ("sector_sums", P(C.c_double)), ("evals", C.c_uint64), ("n_final", C.c_uint64),
                 ("status", C.c_int32), ("deform_violations", C.c_int32),
                 ("kernel_ms", C.c_double), ("algo_flops", C.c_double),
-                ("latency_ms", C.c_double), ("steps", C.c_int32), ("reserved", C.c_int32)]
+                ("latency_ms", C.c_double), ("steps", C.c_int32), ("lambda_halvings", C.c_int32)]
 
 
 class qmc_tune_choice(C.Structure):
@@ -86,7 +86,7 @@ class qmc_class_stat(C.Structure):
 class qmc_request(C.Structure):
     _fields_ = [("kin", P(C.c_double)), ("rel_err_target", C.c_double), ("n0", C.c_uint64),
                 ("n_max", C.c_uint64), ("m", C.c_int32), ("seed", C.c_uint64),
-                ("z", P(C.c_uint32))]
+                ("z", P(C.c_uint32)), ("lambda_halvings", C.c_int32), ("pad", C.c_int32)]
 
 
 _SIGS = {
@@ -351,6 +351,7 @@ class Request:
         out["latency_ms"] = res.latency_ms
         out["steps"] = res.steps
         out["n_final"] = res.n_final
+        out["lambda_halvings"] = res.lambda_halvings
         return out
 
     def poll(self):
@@ -359,7 +360,8 @@ class Request:
         if rc == QMC_PENDING:
             return None
         out = self.plan._pack(res, coeff, None, None, 1)
-        out.update(rc=rc, latency_ms=res.latency_ms, steps=res.steps, n_final=res.n_final)
+        out.update(rc=rc, latency_ms=res.latency_ms, steps=res.steps, n_final=res.n_final,
+                   lambda_halvings=res.lambda_halvings)
         return out
 
     def cancel(self):
@@ -369,12 +371,12 @@ class Request:
         lib().qmc_release(self.plan.ctx.h, self.ticket)
 
 
-def submit(plan, kin, target, n0, n_max, m, seed, z):
+def submit(plan, kin, target, n0, n_max, m, seed, z, lambda_halvings=0):
     """Queue one request of `plan` at kinematic vector `kin`."""
     kin = np.ascontiguousarray(kin, dtype=np.float64)
     z = np.ascontiguousarray(z, dtype=np.uint32)
     req = qmc_request(_dptr(kin), float(target), int(n0), int(n_max), int(m), int(seed),
-                      z.ctypes.data_as(P(C.c_uint32)))
+                      z.ctypes.data_as(P(C.c_uint32)), int(lambda_halvings), 0)
     t = C.c_uint64()
     plan.ctx.check(lib().qmc_submit(plan.ctx.h, plan.h, C.byref(req), C.byref(t)))
     return Request(plan, t.value)

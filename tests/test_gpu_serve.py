@@ -97,3 +97,26 @@ def test_deformation_violation_reported():
                    4, 1, Z).wait(60)
     assert r["rc"] == -6 and r["violations"] > 0
     plan.close()
+
+
+def test_lambda_backoff_recovers():
+    """lambda = 1 violates the sign conditions for the non-planar vertex at
+    s = 4.5 (the plain request retires with QMC_EDEFORM); with back-offs the
+    violating sectors run at lambda/2^k, the request converges, and its
+    result agrees with the one at a safe lambda within the errors."""
+    print("serve: lambda back-off", flush=True)
+    plan, info = gpu_plan("np_vertex", lam=1.0)
+    safe, _ = gpu_plan("np_vertex", lam=0.25)
+    kin = fe.kin_vector(info, {"s": 4.5, "msq": 1.0})
+    plain = qmc.submit(plan, kin, 1e-3, 1 << 12, 1 << 20, 8, 3, Z).wait(120)
+    assert plain["rc"] == -6 and plain["lambda_halvings"] == 0
+    r = qmc.submit(plan, kin, 1e-3, 1 << 12, 1 << 20, 8, 3, Z, lambda_halvings=4).wait(120)
+    assert r["rc"] == 0 and 1 <= r["lambda_halvings"] <= 4 and r["violations"] == 0
+    ref = qmc.submit(safe, kin, 1e-3, 1 << 12, 1 << 20, 8, 3, Z).wait(120)
+    assert ref["rc"] == 0
+    err = np.hypot(r["err_re"], r["err_im"]) + np.hypot(ref["err_re"], ref["err_im"])
+    assert np.all(np.abs(r["mean"] - ref["mean"]) <= 5 * err + 1e-12)
+    with pytest.raises(qmc.QMCError):
+        qmc.submit(plan, kin, 1e-3, 1 << 12, 1 << 20, 8, 3, Z, lambda_halvings=17)
+    plan.close()
+    safe.close()
