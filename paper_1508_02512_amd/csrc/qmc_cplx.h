@@ -8,7 +8,9 @@
 // negative.  Points where Im F(z) > 0 or Re U(z) <= 0 are counted as sign
 // violations.  The pole subtraction of Eq. 11 uses the corner values of the
 // deformed integrand (the deformation vanishes on t_j = 0 in z_j but not
-// in the other variables, so every corner is a full evaluation).
+// in the other variables, so every corner is a full evaluation).  The
+// Jacobian determinant comes from an LDL^T factorisation of a complex
+// symmetric matrix similar to dz/dt (see leaf()).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -66,49 +68,42 @@ __device__ __forceinline__ cd cexp_(cd x)
     return {e * c, e * s};
 }
 
+// prod_j z_j^e_j for 4-bit wave-uniform exponents, powers formed on the fly
+// (no tables of z^2, z^3: the leaf's register budget goes to the Jacobian)
 template <int DM>
-__device__ __forceinline__ cd cmonomial(uint32_t e, const cd *z, const cd *z2, const cd *z3)
+__device__ __forceinline__ cd cmonomial(uint32_t e, const cd *z)
 {
     cd v = {1.0, 0.0};
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
         const uint32_t ej = (e >> (4 * j)) & 15u;
         if (ej == 0u) continue;
-        if (ej == 1u) {
-            v = cmul(v, z[j]);
-        } else if (ej == 2u) {
-            v = cmul(v, z2[j]);
-        } else if (ej == 3u) {
-            v = cmul(v, z3[j]);
-        } else {
-            cd p = cmul(z2[j], z2[j]);
+        cd p = z[j];
+        if (ej >= 2u) {
+            const cd z2 = cmul(z[j], z[j]);
+            p = ej == 2u ? z2 : cmul(z2, ej == 3u ? z[j] : z2);
             for (uint32_t k = 4u; k < ej; ++k) p = cmul(p, z[j]);
-            v = cmul(v, p);
         }
+        v = cmul(v, p);
     }
     return v;
 }
 
 template <int DM>
-__device__ __forceinline__ double rmonomial(uint32_t e, const double *t, const double *t2,
-                                            const double *t3)
+__device__ __forceinline__ double rmonomial(uint32_t e, const double *t)
 {
     double v = 1.0;
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
         const uint32_t ej = (e >> (4 * j)) & 15u;
         if (ej == 0u) continue;
-        if (ej == 1u) {
-            v *= t[j];
-        } else if (ej == 2u) {
-            v *= t2[j];
-        } else if (ej == 3u) {
-            v *= t3[j];
-        } else {
-            double p = t2[j] * t2[j];
+        double p = t[j];
+        if (ej >= 2u) {
+            const double t2 = t[j] * t[j];
+            p = ej == 2u ? t2 : t2 * (ej == 3u ? t[j] : t2);
             for (uint32_t k = 4u; k < ej; ++k) p *= t[j];
-            v *= p;
         }
+        v *= p;
     }
     return v;
 }
@@ -131,89 +126,84 @@ template <int DM, int KS, int K>
 __device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &P, int X,
                                      cd (&h)[K])
 {
-    double tp[DM], op[DM], tp2[DM], tp3[DM];
+    double tp[DM], op[DM];
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
         const bool zero = j < KS && ((X >> j) & 1);
         tp[j] = zero ? 0.0 : P.t[j];
         op[j] = zero ? 1.0 : P.omt[j];
-        tp2[j] = tp[j] * tp[j];
-        tp3[j] = tp2[j] * tp[j];
     }
     const int d = S->dim;
     const double lam = P.lam;
-    // gradient and Hessian of F at the real point
-    double g[DM], H[DM][DM];
+    // gradient of F at the real point
+    double g[DM];
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
         double s = 0.0;
         if (j < d)
             for (int q = S->d1[j]; q < S->d1[j + 1]; ++q)
-                s = fma(P.dcoef[q], rmonomial<DM>(P.dexp[q], tp, tp2, tp3), s);
+                s = fma(P.dcoef[q], rmonomial<DM>(P.dexp[q], tp), s);
         g[j] = s;
     }
-#pragma unroll
-    for (int j = 0; j < DM; ++j) {
-#pragma unroll
-        for (int k = j; k < DM; ++k) {
-            double s = 0.0;
-            if (k < d) {
-                const int idx = j * QMC_DMAX - j * (j - 1) / 2 + (k - j);
-                for (int q = S->d2[idx]; q < S->d2[idx + 1]; ++q)
-                    s = fma(P.dcoef[q], rmonomial<DM>(P.dexp[q], tp, tp2, tp3), s);
-            }
-            H[j][k] = s;
-            H[k][j] = s;
-        }
-    }
-    // phi_j = 1 - i lambda (1 - t_j) g_j, z_j = t_j phi_j
-    cd phi[DM], z[DM], z2[DM], z3[DM];
+    // q_j = lambda (1 - t_j) g_j, phi_j = 1 - i q_j, z_j = t_j phi_j
     double qv[DM];
+    cd z[DM];
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
         qv[j] = lam * op[j] * g[j];
-        phi[j] = {1.0, -qv[j]};
         z[j] = {tp[j], -tp[j] * qv[j]};
-        z2[j] = cmul(z[j], z[j]);
-        z3[j] = cmul(z2[j], z[j]);
     }
-    // Jacobian J = I + i M, M_jk = -lambda (delta_jk (1 - 2 t_j) g_j + t_j (1 - t_j) H_jk);
-    // rows beyond the sector's dimension are identity.  Its Hermitian part
-    // after a diagonal similarity is the identity, so elimination without
-    // pivoting is stable.
-    cd J[DM][DM];
+    // Jacobian dz/dt = I + i M with M = -lambda (T H + diag((1 - 2t) g)),
+    // T = diag(t (1 - t)), H the Hessian of F.  With s_j = sqrt(lambda t_j
+    // (1 - t_j)) the similarity S^-1 (I + i M) S gives
+    //     det(dz/dt) = det(I + i A),  A = -S H S - lambda diag((1 - 2t) g),
+    // A real symmetric: I + i A is complex symmetric with identity real
+    // part, so an LDL^T factorisation without pivoting is stable.  Its lower
+    // triangle is packed row by row; rows beyond the sector's dimension are
+    // identity.
+    double sj[DM];
 #pragma unroll
-    for (int j = 0; j < DM; ++j)
+    for (int j = 0; j < DM; ++j) sj[j] = j < d ? sqrt(lam * tp[j] * op[j]) : 0.0;
+    constexpr int NT = DM * (DM + 1) / 2;
+    cd J[NT];
 #pragma unroll
-        for (int k = 0; k < DM; ++k) {
-            double m = 0.0;
-            if (j < d && k < d) {
-                m = -lam * tp[j] * op[j] * H[j][k];
-                if (j == k) m -= lam * (op[j] - tp[j]) * g[j];
+    for (int j = 0; j < DM; ++j) {
+#pragma unroll
+        for (int k = 0; k <= j; ++k) {
+            double hs = 0.0;
+            if (j < d) {
+                const int idx = k * QMC_DMAX - k * (k - 1) / 2 + (j - k);
+                for (int q = S->d2[idx]; q < S->d2[idx + 1]; ++q)
+                    hs = fma(P.dcoef[q], rmonomial<DM>(P.dexp[q], tp), hs);
             }
-            J[j][k] = {j == k ? 1.0 : 0.0, m};
+            double a = -(sj[j] * hs) * sj[k];
+            if (j == k && j < d) a -= lam * (op[j] - tp[j]) * g[j];
+            J[j * (j + 1) / 2 + k] = {j == k ? 1.0 : 0.0, a};
         }
+    }
     cd det = {1.0, 0.0};
 #pragma unroll
     for (int c = 0; c < DM; ++c) {
-        det = cmul(det, J[c][c]);
-        const cd inv = crecip(J[c][c]);
+        const cd dc = J[c * (c + 1) / 2 + c];
+        det = cmul(det, dc);
+        const cd inv = crecip(dc);
 #pragma unroll
         for (int r = c + 1; r < DM; ++r) {
-            const cd f = cmul(J[r][c], inv);
+            const cd f = cmul(J[r * (r + 1) / 2 + c], inv);
 #pragma unroll
-            for (int k = c + 1; k < DM; ++k) J[r][k] = csub(J[r][k], cmul(f, J[c][k]));
+            for (int k = c + 1; k <= r; ++k)
+                J[r * (r + 1) / 2 + k] = csub(J[r * (r + 1) / 2 + k], cmul(f, J[k * (k + 1) / 2 + c]));
         }
     }
     // U(z), F(z)
     cd U = {0.0, 0.0}, F = {0.0, 0.0};
     for (int q = S->um[0]; q < S->um[QMC_NMASK]; ++q) {
-        const cd v = cmonomial<DM>(P.texp[q], z, z2, z3);
+        const cd v = cmonomial<DM>(P.texp[q], z);
         U.r = fma(P.coef[q], v.r, U.r);
         U.i = fma(P.coef[q], v.i, U.i);
     }
     for (int q = S->fm[0]; q < S->fm[QMC_NMASK]; ++q) {
-        const cd v = cmonomial<DM>(P.texp[q], z, z2, z3);
+        const cd v = cmonomial<DM>(P.texp[q], z);
         F.r = fma(P.coef[q], v.r, F.r);
         F.i = fma(P.coef[q], v.i, F.i);
     }
@@ -237,7 +227,7 @@ __device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &
         if (ai == QMC_NO_INT)
             pre = cmul(pre, cexp_(cscale(lphi, S->a[j])));
         else if (ai != 0)
-            pre = cmul(pre, cpowi(phi[j], ai));
+            pre = cmul(pre, cpowi(cd{1.0, -qv[j]}, ai));
     }
     h[0] = pre;
 #pragma unroll
@@ -413,8 +403,16 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
 // per work-group when the grid covers the list, a persistent loop when the
 // grid is smaller.  Each item writes only its own slot, so the result does
 // not depend on the grid.
+// The deformed integrand is bound by scalar work (wave-uniform term loops
+// and exponent decoding) and its latency, so it is built for four waves per
+// SIMD, which lets one wave's scalar and another's vector instructions issue
+// together.  The register allocator spills 40-300 VGPRs per lane to
+// scratch for that; measured on the gg -> HH double boxes and the
+// non-planar vertex, one wave per SIMD (no spills) is 3.1x slower, two
+// 1.9x, three 1.2x, six about the same, eight 1.15x.
 template <int DM, int KS, int K>
-__global__ __launch_bounds__(QMC_BLOCK) void qmc_eval_cplx(qmc_launch_args A)
+__global__ __launch_bounds__(QMC_BLOCK)
+__attribute__((amdgpu_waves_per_eu(4, 8))) void qmc_eval_cplx(qmc_launch_args A)
 {
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
         qmc_eval_cplx_item<DM, KS, K>(A, item);
