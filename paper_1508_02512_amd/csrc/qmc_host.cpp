@@ -543,10 +543,20 @@ int qmc_sector_mode(const qmc_plan *plan, int s, const double *coef, double *lam
     return qmc_cplx_dm(h.dim);
 }
 
+int qmc_class_grid(const qmc_class &c)
+{
+    const int items = c.end - c.begin;
+    const int grid = c.grid > 0 ? std::min(c.grid, items) : items;
+    // a launch may hold fewer than 2^32 work-items in total; the kernels
+    // loop over the items with stride gridDim, so a capped grid still
+    // covers every item
+    return std::min(grid, QMC_MAX_GRID);
+}
+
 hipError_t qmc_launch_class(const qmc_plan *plan, const qmc_class &c, const qmc_launch_args &A,
                             hipStream_t stream)
 {
-    const int grid = c.grid > 0 ? std::min(c.grid, c.end - c.begin) : c.end - c.begin;
+    const int grid = qmc_class_grid(c);
     if (c.deform) return qmc_launch_cplx(c.dm, c.ks, c.kb, A, grid, stream);
     return qmc_launch_real(c.ks, c.kb, plan->opts.precision == QMC_FP32_EVAL, A, grid, stream);
 }
@@ -1029,7 +1039,7 @@ extern "C" int qmc_job_class_stats(const qmc_job *job, qmc_class_stat *out, int3
         st.poles = c.ks;
         st.width = c.dm;
         st.points_per_lane = c.ppl;
-        st.grid = c.grid > 0 ? std::min(c.grid, items) : items;
+        st.grid = qmc_class_grid(c);
         st.items = items;
         st.precision = job->plan->opts.precision;
         st.evals = c.evals;

@@ -84,6 +84,9 @@ struct qmc_plan {
     uint32_t *d_dexp = nullptr;
 };
 
+// largest grid of one launch: (2^32 - 1) work-items / QMC_BLOCK lanes
+constexpr int QMC_MAX_GRID = (int)(0xffffffffu / QMC_BLOCK);
+
 struct qmc_class {                   // items launched by one kernel instance
     int ks = 0, kb = 1, deform = 0, dm = 0;
     int begin = 0, end = 0;
@@ -93,6 +96,8 @@ struct qmc_class {                   // items launched by one kernel instance
     double flops = 0.0;              // algorithmic flops of one launch
 };
 
+
+int qmc_class_grid(const qmc_class &c);
 
 struct qmc_job {
     qmc_ctx *ctx = nullptr;

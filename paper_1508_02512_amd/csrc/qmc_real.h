@@ -386,14 +386,18 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
 // per work-group when the grid covers the list, a persistent loop when the
 // grid is smaller.  Each item writes only its own slot, so the result does
 // not depend on the grid.
-// Minimum waves per SIMD the register allocator must allow (measured on
-// the planar double box; more occupancy spills instead): two for three
-// poles, and for four poles in FP32; the other classes reach three or more
-// by themselves, the FP64 four-pole class runs fastest at one.
+// Minimum waves per SIMD the register allocator must allow, i.e. how far
+// it spills to buy occupancy.  Chosen per class from a sweep on the planar
+// double box (n = 1000003, 4 shifts, ms per launch, FP64 / FP32):
+//   poles 1: 4 waves (41.8 vs 47.9 ms) / unconstrained
+//   poles 2: 4 (77.4 vs 105.3) / 6 (47.9 vs 58.7)
+//   poles 3: 2 (116.8; 3 gives 127.5) / 4 (75.6 vs 88.6)
+//   poles 4: 1 (164.5; 2 gives 201.1) / 3 (83.7 vs 103.0)
 template <int KS, typename T>
 constexpr int min_waves()
 {
-    return KS == 3 || (KS == 4 && sizeof(T) == 4) ? 2 : 1;
+    if (sizeof(T) == 8) return KS == 1 || KS == 2 ? 4 : (KS == 3 ? 2 : 1);
+    return KS <= 1 ? 1 : (KS == 2 ? 6 : (KS == 3 ? 4 : 3));
 }
 
 template <int KS, int K, typename T>

@@ -103,3 +103,31 @@ def test_class_stats_account_for_the_whole_run():
     job.fetch()
     assert all(c["ms"] == -1.0 for c in job.class_stats())
     job.close()
+
+
+def test_more_items_than_one_launch_can_hold():
+    """One work-group per item with more items than a launch may hold
+    (2^32 work-items): the two-pole class of the double box with one
+    lattice point per lane, n = 4194301, 4 shifts, has 272 x 4 x 16384
+    items.  The grid is capped and the item loop covers the rest; the
+    result equals the default tiling's up to summation order."""
+    print("batch: > 2^24 items in one class", flush=True)
+    n = 4194301
+    sh = shift_table(9, 4, 8)
+    kin = None
+    out = []
+    for ppl in (1, 0):
+        plan, info = gpu_plan("doublebox", ppl=ppl)
+        kin = fe.kin_vector(info, {"s": -3.0, "t": -1.0})
+        job = plan.bind(kin, (n, lattice(n)), sh)
+        st = job.class_stats()
+        if ppl == 1:
+            two = [c for c in st if c["poles"] == 2][0]
+            assert two["items"] > 0xffffffff // 256 and two["grid"] == 0xffffffff // 256
+        job.run()
+        out.append(job.fetch())
+        job.close()
+        plan.close()
+    a, b = out
+    assert np.allclose(a["mean"], b["mean"], rtol=1e-12, atol=0)
+    assert np.allclose(a["err_re"], b["err_re"], rtol=1e-9, atol=0)
