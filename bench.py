@@ -353,11 +353,14 @@ def main():
         wall32 = time.perf_counter() - t2
         dev = np.abs(res32["mean"][0] - res["mean"][0]) / np.maximum(
             np.hypot(res["err_re"][0], res["err_im"][0]), 1e-300)
+        rel = np.abs(res32["mean"][0] - res["mean"][0]) / np.maximum(
+            np.abs(res["mean"][0]), 1e-300)
         fp32 = {"value": res32["evals"] * args.steps / wall32, "unit": "evals/s",
                 "ms_per_step": wall32 / args.steps * 1e3,
                 "kernel_ms_per_step": float(np.mean(k32)),
                 "achieved_tflops": res32["algo_flops"] / (float(np.mean(k32)) / 1e3) / 1e12,
-                "max_dev_vs_fp64_in_sigma": float(dev.max())}
+                "max_dev_vs_fp64_in_sigma": float(dev.max()),
+                "rel_dev_vs_fp64_per_order": [float(x) for x in rel]}
         if not args.no_time_to_target:
             fp32["time_to_1e-3"], _ = time_to_target(plan32, "fp32")
         job32.close()

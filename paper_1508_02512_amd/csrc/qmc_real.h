@@ -390,13 +390,14 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
 // it spills to buy occupancy.  Chosen per class from a sweep on the planar
 // double box (n = 1000003, 4 shifts, ms per launch, FP64 / FP32):
 //   poles 1: 4 waves (41.8 vs 47.9 ms) / unconstrained
-//   poles 2: 4 (77.4 vs 105.3) / 6 (47.9 vs 58.7)
+//   poles 2: 3 (82.8 vs 105.3; 4 waves, 77.4 ms, spill 39 VGPRs and write
+//            ~390 GB of scratch to HBM per launch) / 6 (47.9 vs 58.7)
 //   poles 3: 2 (116.8; 3 gives 127.5) / 4 (75.6 vs 88.6)
 //   poles 4: 1 (164.5; 2 gives 201.1) / 3 (83.7 vs 103.0)
 template <int KS, typename T>
 constexpr int min_waves()
 {
-    if (sizeof(T) == 8) return KS == 1 || KS == 2 ? 4 : (KS == 3 ? 2 : 1);
+    if (sizeof(T) == 8) return KS == 1 ? 4 : (KS == 2 ? 3 : (KS == 3 ? 2 : 1));
     return KS <= 1 ? 1 : (KS == 2 ? 6 : (KS == 3 ? 4 : 3));
 }
 
