@@ -209,6 +209,41 @@ def vertex_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, n_total=1000
     return out
 
 
+def hh_box_scan(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log):
+    """Section IV.A workload: the one-loop gg -> HH box at 1000 points
+    s = 70000 .. 500000 GeV^2 (t = -6000, M_t = 172, M_H = 125) in one
+    batched bind, n = 262139, 8 shifts, lambda = 0.5."""
+    import numpy as np
+    import torch
+
+    secs, info = fe.decompose(PROBLEMS["hh_box"])
+    plan = ctx.plan(fe.sector_arrays(secs, info), info, 0, fe.prefactor_series(info, 12),
+                    lam=0.5)
+    svals = np.linspace(70000.0, 500000.0, 1000)
+    kin = np.stack([fe.kin_vector(info, {"s": float(v), "t": -6000.0, "mtsq": MT2,
+                                         "mhsq": MH2}) for v in svals])
+    n = 262139
+    job = plan.bind(kin, (n, lattice(n)), shift_table(0, 8, 8))
+    job.run()
+    job.fetch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    job.run()
+    r = job.fetch()
+    wall = time.perf_counter() - t0
+    job.close()
+    plan.close()
+    mean = r["mean"][:, 0]
+    rel = np.hypot(r["err_re"][:, 0], r["err_im"][:, 0]) / np.abs(mean)
+    out = {"points": len(svals), "seconds": wall, "ms_per_point": wall / len(svals) * 1e3,
+           "evals_per_s": r["evals"] / wall, "max_rel_err": float(rel.max()),
+           "points_rel_err_below_1e-4": int((rel < 1e-4).sum()),
+           "violations": int(r["violations"])}
+    log(f"hh_box scan: {out['ms_per_point']:.2f} ms/point, max rel err {out['max_rel_err']:.1e}, "
+        f"{out['points_rel_err_below_1e-4']} points below 1e-4")
+    return out
+
+
 def batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, fp32):
     """512 kinematic points of the all-massive two-loop planar vertex,
     s uniform in [-10, 10] without |s - 4| < 0.05 (numpy PCG64 seed 0),
@@ -370,6 +405,7 @@ def main():
     extra = None
     if args.extra:
         extra = {"np_vertex": vertex_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log),
+                 "hh_box_scan": hh_box_scan(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log),
                  "batch_fp64": batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log,
                                            False),
                  "batch_fp32": batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log,

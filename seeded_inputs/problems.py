@@ -168,6 +168,16 @@ _SP_HH = {
     ("p1", "p3"): {"s": "1/2", "t": "1/2", "mhsq": "-1/2"},
 }
 
+# I_A (Section IV.A): one-loop box for gg -> HH with four top-quark lines,
+# k^2-mt^2, (k+p1)^2-mt^2, (k-p2)^2-mt^2, (k+p1-p4)^2-mt^2 = (k-p2+p3)^2-mt^2.
+# The paper's measure there is d^D k / (2 pi)^D, i pi^(D/2) / (2 pi)^D times
+# the measure used here.
+HH_BOX = Problem(
+    "hh_box", 1, ("p1", "p2", "p3"), ("s", "t", "mtsq", "mhsq"), _SP_HH,
+    (_P([1], mass="mtsq"), _P([1], {"p1": 1}, mass="mtsq"),
+     _P([1], {"p2": -1}, mass="mtsq"), _P([1], {"p2": -1, "p3": 1}, mass="mtsq")),
+    note="one-loop box for gg -> HH (Section IV.A, threshold at s = 4 mt^2)")
+
 # I_C (Section IV.C): planar double box with four top-quark lines,
 # k1^2, (k1-p1)^2, (k1+p2)^2, (k1-k2-p1)^2-mt^2, k2^2-mt^2,
 # (k1+p2-k2-p3)^2-mt^2, (k1-k2+p2)^2-mt^2.
@@ -198,4 +208,5 @@ PROBLEMS = {p.name: p for p in (BUBBLE, BUBBLE_MASSIVE, BOX, TRIANGLE_OFFSHELL,
                                 DOUBLEBOX,
                                 DOUBLEBOX_OFFSHELL, DOUBLEBOX_OFF14,
                                 DOUBLEBOX_OFF24, DOUBLEBOX_OFF34,
-                                NP_VERTEX, TRIANGLE2L, HH_PLANAR, HH_NONPLANAR)}
+                                NP_VERTEX, TRIANGLE2L, HH_BOX, HH_PLANAR,
+                                HH_NONPLANAR)}

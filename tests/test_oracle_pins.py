@@ -317,3 +317,17 @@ def test_oracle_tables2_3_leading_pole(table, lam):
     P = p_coefficients(list(res["orders"]), res["mean"], res["err_re"], res["err_im"],
                        HH_POINT["s"])
     check_against(P, {"P2": tab["qmc"]["P2"]}, nsig=5.0)
+
+
+def test_oracle_hh_box_threshold():
+    """Section IV.A: Re(I_A) vanishes below the top-pair threshold
+    s = 4 M_t^2 = 118336 and not above it.  With the paper's d^Dk/(2 pi)^D
+    measure I_A = i pi^(D/2)/(2 pi)^D J, so Re(I_A) = 0 is Im J = 0 for the
+    J computed here (finite: one order, eps^0)."""
+    from seeded_inputs.problems import HH_POINT
+    below = _run("hh_box", {**HH_POINT, "s": 80000.0}, 10007, m=8, lam=0.5)
+    above = _run("hh_box", {**HH_POINT, "s": 200000.0}, 10007, m=8, lam=0.5)
+    assert below["orders"] == [0] and below["counts"][:2].sum() == 0
+    assert abs(below["mean"][0].imag) <= 5 * below["err_im"][0]
+    assert below["mean"][0].real > 1e3 * below["err_re"][0]
+    assert above["mean"][0].imag > 100 * above["err_im"][0]
