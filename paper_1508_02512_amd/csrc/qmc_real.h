@@ -229,17 +229,34 @@ __device__ __forceinline__ void mobius_series(cptr<qmc_sec_dev> S, Point<KS, K, 
     for (int Y = 0; Y < N; ++Y)
         P.bad |= !(mobius::corner<KS, T>(P.SU, Y) > T(0)) |
                  !(mobius::corner<KS, T>(P.SF, Y) > T(0));
+    // log U is folded into B and X before log F is formed, so the two
+    // logarithm vectors are never live together
     T B[N], H[N];
     {
-        T lU[N], lF[N], X[N];
-        mobius::log<KS, T>(P.SU, lU);
-        mobius::log<KS, T>(P.SF, lF);
+        T X[N];
+        {
+            T l[N];
+            mobius::log<KS, T>(P.SU, l);
 #pragma unroll
-        for (int Y = 0; Y < N; ++Y) {
-            B[Y] = fma(T(S->u1), lU[Y], T(S->f1) * lF[Y]);
-            X[Y] = fma(T(S->u0), lU[Y], T(S->f0) * lF[Y]);
+            for (int Y = 0; Y < N; ++Y) {
+                B[Y] = T(S->u1) * l[Y];
+                X[Y] = T(S->u0) * l[Y];
+            }
+        }
+        {
+            T l[N];
+            mobius::log<KS, T>(P.SF, l);
+#pragma unroll
+            for (int Y = 0; Y < N; ++Y) {
+                B[Y] = fma(T(S->f1), l[Y], B[Y]);
+                X[Y] = fma(T(S->f0), l[Y], X[Y]);
+            }
         }
         B[0] += P.LN;
+        // keep B and X formed here: otherwise the scheduler sinks their fmas
+        // into the accumulation and both logarithm vectors stay live
+#pragma unroll
+        for (int Y = 0; Y < N; ++Y) asm volatile("" : "+v"(B[Y]), "+v"(X[Y]));
         mobius::exp<KS, T>(X, H);
     }
 #pragma unroll
@@ -387,17 +404,17 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
 // grid is smaller.  Each item writes only its own slot, so the result does
 // not depend on the grid.
 // Minimum waves per SIMD the register allocator must allow, i.e. how far
-// it spills to buy occupancy.  Chosen per class from a sweep on the planar
+// it spills to buy occupancy.  Chosen per class from sweeps on the planar
 // double box (n = 1000003, 4 shifts, ms per launch, FP64 / FP32):
-//   poles 1: 4 waves (41.8 vs 47.9 ms) / unconstrained
-//   poles 2: 3 (82.8 vs 105.3; 4 waves, 77.4 ms, spill 39 VGPRs and write
-//            ~390 GB of scratch to HBM per launch) / 6 (47.9 vs 58.7)
-//   poles 3: 2 (116.8; 3 gives 127.5) / 4 (75.6 vs 88.6)
-//   poles 4: 1 (164.5; 2 gives 201.1) / 3 (83.7 vs 103.0)
+//   poles 1: 4 waves (41.3 vs 47.9 ms) / unconstrained
+//   poles 2: 3 (80.8 vs 105.3; 4 waves, 77.4 ms, spill 39 VGPRs and write
+//            ~390 GB of scratch to HBM per launch) / 6 (45.7 vs 58.7)
+//   poles 3: 3 (99.2; 2 gives 116.6, 4 gives 106.4) / 4 (73.3 vs 88.6)
+//   poles 4: 2 (103.1; 1 gives 161.6, 3 gives 115.1) / 3 (82.2 vs 103.0)
 template <int KS, typename T>
 constexpr int min_waves()
 {
-    if (sizeof(T) == 8) return KS == 1 ? 4 : (KS == 2 ? 3 : (KS == 3 ? 2 : 1));
+    if (sizeof(T) == 8) return KS == 1 ? 4 : (KS == 2 || KS == 3 ? 3 : 2);
     return KS <= 1 ? 1 : (KS == 2 ? 6 : (KS == 3 ? 4 : 3));
 }
 
