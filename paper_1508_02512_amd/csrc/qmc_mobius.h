@@ -70,6 +70,35 @@ __device__ __forceinline__ void mul(const T (&f)[1 << KS], const T (&g)[1 << KS]
     }
 }
 
+// f <- f * g / (q + 1) in place, forming only the coefficients with at
+// most MAXPC variables and zeroing the others.  A proper subset of Y has a
+// smaller mask, so visiting Y in decreasing order reads every f^[A],
+// A subset of Y, before it is overwritten.
+template <int KS, int MAXPC, typename T>
+__device__ __forceinline__ void mul_inplace(T (&f)[1 << KS], const T (&g)[1 << KS], T scale)
+{
+    constexpr int N = 1 << KS;
+#pragma unroll
+    for (int Y = N - 1; Y >= 0; --Y) {
+        if (__builtin_popcount(Y) > MAXPC) {
+            f[Y] = T(0);
+            continue;
+        }
+        T s = 0;
+#pragma unroll
+        for (int A = 0; A < N; ++A) {
+            if ((A & ~Y) != 0) continue;
+            const int R = Y & ~A;
+#pragma unroll
+            for (int C = 0; C < N; ++C) {
+                if ((C & ~A) != 0) continue;
+                s = fma(f[A], g[R | C], s);
+            }
+        }
+        f[Y] = s * scale;
+    }
+}
+
 // corner value f(Y) = sum_{A subset Y} f^[A]
 template <int KS, typename T>
 __device__ __forceinline__ T corner(const T (&f)[1 << KS], int Y)
@@ -119,6 +148,15 @@ __device__ __forceinline__ void after(T (&v)[N], T dep)
 #pragma unroll
         for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i]) : "v"(dep));
     }
+}
+
+// Phase fence: every v[i] is made to depend on dep (the last value a phase
+// produces), so no consumer of v starts before the whole phase is done.
+template <int N, typename T>
+__device__ __forceinline__ void fence(T (&v)[N], T dep)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i]) : "v"(dep));
 }
 
 // r = log(1 + x); with X0ZERO the caller guarantees x^[0] = 0, so the

@@ -205,11 +205,11 @@ struct Accum {
         }
         if constexpr (Q + 1 < K) {
             constexpr int MAXPC = K - 2 - Q < KS ? K - 2 - Q : KS;
-            T nt[N];
-            mobius::mul<KS, MAXPC, T>(H, B, nt);
-#pragma unroll
-            for (int Y = 0; Y < N; ++Y)
-                H[Y] = __builtin_popcount(Y) <= MAXPC ? nt[Y] * (T(1) / T(Q + 1)) : T(0);
+            // one level at a time (fences): overlapping this level's series
+            // chains with the next level's product keeps both live
+            mobius::fence<N, T>(H, g[K - 1]);
+            mobius::mul_inplace<KS, MAXPC, T>(H, B, T(1) / T(Q + 1));
+            mobius::fence<N, T>(H, H[0]);
             Accum<KS, K, Q + 1, T>::run(S, P, B, H, g);
         }
     }
@@ -258,6 +258,9 @@ __device__ __forceinline__ void mobius_series(cptr<qmc_sec_dev> S, Point<KS, K, 
 #pragma unroll
         for (int Y = 0; Y < N; ++Y) asm volatile("" : "+v"(B[Y]), "+v"(X[Y]));
         mobius::exp<KS, T>(X, H);
+        // the accumulation starts when the whole exponential is done:
+        // overlapping the two keeps both phases' temporaries live
+        mobius::fence<N, T>(H, H[N - 1]);
     }
 #pragma unroll
     for (int o = 0; o < K; ++o) g[o] = 0;
