@@ -9,6 +9,7 @@ import pytest
 
 from gpu_util import compare_sectors, ctx, gpu_plan, sample_sectors
 from oracle import qmc as oq
+from oracle.decompose import decompose as odec
 from paper_1508_02512_amd import frontend as fe
 from seeded_inputs.lattice import lattice
 from seeded_inputs.problems import PROBLEMS
@@ -121,3 +122,37 @@ def test_invalid_inputs_raise():
     with pytest.raises(qmc.QMCError) as e:
         ctx().plan(bad, info, 0, fe.prefactor_series(info, 8))
     assert e.value.code == -3
+
+
+def test_double_box_benchmark_config_sampled():
+    """The benchmark workload itself: planar double box, all 882 sectors,
+    n = 1000003, 16 shifts, in the launch shape bench.py times (automatic
+    points per lane).  Sampled outputs the oracle computes one by one: the
+    shift-0 sums of every third pole-free sector and of four one-pole sectors at
+    the full lattice size.  Properties of the whole result: finite, and the
+    eps^-4 .. eps^0 coefficients agree with a 16x smaller lattice within
+    the errors."""
+    print("doublebox n=1000003 m=16 (benchmark config)", flush=True)
+    plan, info = gpu_plan("doublebox")
+    kin_vals = {"s": -3.0, "t": -1.0}
+    kin = fe.kin_vector(info, kin_vals)
+    n = 1000003
+    sh = shift_table(0, 16, 8)
+    res = plan.integrate(kin, (n, lattice(n)), sh, sector_sums=True)
+    small = plan.integrate(kin, (65521, lattice(65521)), sh)
+    assert np.all(np.isfinite(res["mean"]))
+    err = np.hypot(res["err_re"], res["err_im"]) + np.hypot(small["err_re"], small["err_im"])
+    assert np.all(np.abs(res["mean"] - small["mean"]) <= 6 * err)
+    osecs, oinfo = odec(PROBLEMS["doublebox"])
+    poles = [sum(1 for a in s["a"] if a == -1) for s in osecs]
+    pick = [i for i, p in enumerate(poles) if p == 0][::3] + \
+        [i for i, p in enumerate(poles) if p == 1][::40][:4]
+    z = lattice(n)
+    for s in pick:
+        ns = oq.NumericSector(osecs[s], oinfo, kin_vals)
+        sums, abss, _ = oq.sector_sums(ns, n, z, sh[:1], 2, 0.0, res["sec_lo"],
+                                       plan.info.sec_orders)
+        gpu = res["sector_sums"][0, s, :1]
+        scale = abss[..., 0] + abss[..., 1]
+        assert np.all(np.abs(gpu - sums) <= 1e-12 * scale), s
+    plan.close()
