@@ -72,3 +72,41 @@ def test_dual_lattice_exactness():
     # a dual vector: h = (a, -1, 0) since a*1 - 1*a = 0
     h = np.array([int(z[1]), -1, 0])
     assert abs(np.mean(np.exp(2j * np.pi * (x @ h))) - 1) < 1e-9
+
+
+def test_fast_cbc_equals_brute_force_cbc():
+    """The FFT form of the component-by-component search picks, component by
+    component, the same z as evaluating the P_2 criterion for every
+    candidate directly (n = 101, 5 components, unit weights)."""
+    import math
+
+    import numpy as np
+
+    from seeded_inputs.lattice import cbc_vector, p2_criterion
+    n, d = 101, 5
+    fast, p2 = cbc_vector(n, d)
+    z = [1]
+    for _ in range(1, d):
+        crit = [p2_criterion(n, z + [c]) for c in range(1, n)]
+        best = min(crit)
+        # ties (equal criteria) may resolve to either candidate
+        choice = fast[len(z)]
+        assert math.isclose(crit[choice - 1], best, rel_tol=1e-12, abs_tol=1e-15)
+        z.append(choice)
+    assert math.isclose(p2, p2_criterion(n, fast), rel_tol=1e-10)
+    assert all(math.gcd(v, n) == 1 for v in fast)
+
+
+def test_stored_cbc_vectors():
+    import math
+
+    from seeded_inputs.lattice import CBC_MAX_N, PRIME_SIZES, lattice, p2_criterion
+    for n in PRIME_SIZES:
+        if n > CBC_MAX_N:
+            continue
+        z = [int(v) for v in lattice(n, "cbc")]
+        assert z[0] == 1 and all(0 < v < n and math.gcd(v, n) == 1 for v in z)
+        if n <= 65521:
+            # over all 8 components CBC is at least as good as the Korobov pick
+            k = [int(v) for v in lattice(n)]
+            assert p2_criterion(n, z) <= p2_criterion(n, k) * 1.0000001
