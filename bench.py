@@ -55,6 +55,7 @@ def parse():
                     help="also run one 256 MiB device copy (calibrates HBM counters)")
     ap.add_argument("--serve-seconds", type=float, default=0.25)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-sectors", choices=("iterated", "geometric"), default="geometric")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -108,11 +109,13 @@ def serve_kinematics(rng, kind):
     return "hh_planar", {"s": sv, "t": t, "mtsq": MT2, "mhsq": MH2}
 
 
-def serve_bench(qmc, fe, PROBLEMS, lattice, seconds, rate, fp32, slots, log):
+def serve_bench(qmc, fe, PROBLEMS, lattice, seconds, rate, fp32, slots, log,
+                strategy="geometric"):
     """Poisson request stream (seeded) mixing the one-loop box, the planar
     two-loop box of Section IV.C (I_C) and the non-planar vertex, all at
     physical kinematics, target 1e-3 relative; embedded lattices
-    n = 2^14 .. 2^22 doubling, 8 shifts, up to 4 deformation back-offs."""
+    n = 2^14 .. 2^22 doubling, 8 shifts, up to 4 deformation back-offs;
+    sectors from the given decomposition strategy."""
     import numpy as np
 
     rng = np.random.default_rng(0)
@@ -120,7 +123,7 @@ def serve_bench(qmc, fe, PROBLEMS, lattice, seconds, rate, fp32, slots, log):
     ctx = qmc.Context(0, max_slots=slots)
     plans = {}
     for name, lam in (("box", 0.5), ("hh_planar", 1.0), ("np_vertex", 0.5)):
-        secs, info = fe.decompose(PROBLEMS[name])
+        secs, info = fe.decompose(PROBLEMS[name], strategy)
         plans[name] = (ctx.plan(fe.sector_arrays(secs, info), info, 0,
                                 fe.prefactor_series(info, 12), lam=lam, precision=prec), info)
     z = lattice(1 << 24)
@@ -367,10 +370,20 @@ def main():
                         "max_rel_err": float(rel.max())}, r
         return None, r
 
-    ttt = ttt_cbc = None
+    ttt = ttt_cbc = ttt_geo = None
     if not args.no_time_to_target:
         ttt, r64 = time_to_target(plan, "fp64")
         ttt_cbc, _ = time_to_target(plan, "fp64, CBC vectors", "cbc")
+        # the same integral over the geometric sectors (planning not timed)
+        tp = time.perf_counter()
+        gsecs, ginfo = fe.decompose(PROBLEMS["doublebox"], "geometric")
+        plang = ctx.plan(fe.sector_arrays(gsecs, ginfo), ginfo, 0,
+                         fe.prefactor_series(ginfo, 12))
+        plan_s = time.perf_counter() - tp
+        ttt_geo, _ = time_to_target(plang, "fp64, geometric sectors")
+        if ttt_geo is not None:
+            ttt_geo.update({"sectors": len(gsecs), "host_planning_seconds": plan_s})
+        plang.close()
 
     # FP32-evaluation mode on the same workload
     fp32 = None
@@ -417,10 +430,11 @@ def main():
     serve = None
     if not args.no_serve:
         serve = {
+            "sectors": args.serve_sectors,
             "batched_fp32": serve_bench(qmc, fe, PROBLEMS, lattice, args.serve_seconds,
-                                        args.serve_rate, True, 64, log),
+                                        args.serve_rate, True, 64, log, args.serve_sectors),
             "plain_fp64": serve_bench(qmc, fe, PROBLEMS, lattice, args.serve_seconds,
-                                      args.serve_rate, False, 1, log),
+                                      args.serve_rate, False, 1, log, args.serve_sectors),
         }
 
     out = {
@@ -460,6 +474,7 @@ def main():
                                            for c in stats[-1]]}},
         "time_to_1e-3": ttt,
         "time_to_1e-3_cbc_vectors": ttt_cbc,
+        "time_to_1e-3_geometric_sectors": ttt_geo,
         "fp32_eval": fp32,
         "serve": serve,
         "extra": extra,

@@ -246,7 +246,7 @@ def integrate(problem, kin, n, z, shifts, r=2, lam=0.0, eps_hi=0, nthreads=0,
         per.append(S)
         counts += c.sum(axis=0)
     eps_lo = sec_lo + pref_lo
-    res = assemble(per, [1.0] * len(per), pref_probe, pref_lo, sec_lo, n,
+    res = assemble(per, [float(s.get("D", 1)) for s in sectors], pref_probe, pref_lo, sec_lo, n,
                    eps_lo, eps_hi)
     res["sector_sums"] = per
     res["counts"] = counts

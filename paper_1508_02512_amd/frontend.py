@@ -173,10 +173,11 @@ def symanzik_polynomials(problem):
 
 class _Sec:
     """Exponent matrix + coefficient rows of U and F and the monomial."""
-    __slots__ = ("a", "b", "EU", "CU", "EF", "CF")
+    __slots__ = ("a", "b", "EU", "CU", "EF", "CF", "D")
 
     def __init__(self, a, b, EU, CU, EF, CF):
         self.a, self.b = a, b
+        self.D = 1
         self.EU, self.CU, self.EF, self.CF = EU, CU, EF, CF
 
 
@@ -250,8 +251,33 @@ def _decompose_primary(sec, ex, out, max_depth=64):
         stack.extend(reversed(children))      # first child is processed first
 
 
-def decompose(problem):
-    """Sectors of a problem as a list of dicts plus global info."""
+def _geometric_primary(sec, ex, out):
+    """Sectors of one primary sector from the simplicial cones of the normal
+    fan of Newt(U F) + R^d_{>=0} (module ``geometric``): t_j = prod_k
+    s_k^{V_jk}, Jacobian |det V| prod_k s_k^{sum_j V_jk - 1}."""
+    from . import geometric
+
+    u0, u1, f0, f1 = ex
+    for V, det in geometric.decompose_primary(sec.EU, sec.EF):
+        EU, EF = sec.EU @ V, sec.EF @ V
+        mu, mf = EU.min(axis=0), EF.min(axis=0)
+        cols = V.sum(axis=0)
+        a = [sum(int(V[j, k]) * sec.a[j] for j in range(V.shape[0])) + int(cols[k]) - 1
+             + int(mu[k]) * u0 + int(mf[k]) * f0 for k in range(V.shape[1])]
+        b = [sum(int(V[j, k]) * sec.b[j] for j in range(V.shape[0]))
+             + int(mu[k]) * u1 + int(mf[k]) * f1 for k in range(V.shape[1])]
+        s = _Sec(a, b, EU - mu, sec.CU, EF - mf, sec.CF)
+        s.D = det
+        out.append(s)
+
+
+def decompose(problem, strategy="iterated"):
+    """Sectors of a problem as a list of dicts plus global info.
+
+    strategy "iterated" splits as described above; "geometric" takes the
+    normal fan of each primary sector's Newton polytope (fewer sectors)."""
+    if strategy not in ("iterated", "geometric"):
+        raise ValueError(f"unknown decomposition strategy {strategy!r}")
     U, F, inv = symanzik_polynomials(problem)
     N, L = len(problem.props), problem.loops
     nus = [p.power for p in problem.props]
@@ -264,9 +290,12 @@ def decompose(problem):
         EF, CF = _to_mats(F, l)
         a = [Fraction(nus[j] - 1) for j in range(N) if j != l]
         b = [Fraction(0)] * (N - 1)
-        _decompose_primary(_Sec(a, b, EU, CU, EF, CF), ex, out)
-    sectors = [{"a": s.a, "b": s.b, "EU": s.EU, "CU": s.CU, "EF": s.EF, "CF": s.CF}
-               for s in out]
+        if strategy == "geometric":
+            _geometric_primary(_Sec(a, b, EU, CU, EF, CF), ex, out)
+        else:
+            _decompose_primary(_Sec(a, b, EU, CU, EF, CF), ex, out)
+    sectors = [{"a": s.a, "b": s.b, "EU": s.EU, "CU": s.CU, "EF": s.EF, "CF": s.CF,
+                "D": s.D} for s in out]
     info = {"invariants": inv, "u": ex[:2], "f": ex[2:], "gamma": (Nnu - 2 * L, L),
             "nus": nus, "dim": N - 1}
     return sectors, info
@@ -344,6 +373,7 @@ def sector_arrays(sectors, info):
             "CU": np.array([[float(x) for x in row] for row in s["CU"]]).reshape(-1, ni),
             "EF": np.ascontiguousarray(s["EF"], dtype=np.uint8),
             "CF": np.array([[float(x) for x in row] for row in s["CF"]]).reshape(-1, ni),
+            "D": float(s.get("D", 1)),
             "u": tuple(float(x) for x in info["u"]),
             "f": tuple(float(x) for x in info["f"]),
         })

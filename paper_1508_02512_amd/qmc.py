@@ -215,7 +215,7 @@ class Plan:
                 poly.coef = _dptr(Cm)
             r.u_exp[0], r.u_exp[1] = s["u"]
             r.f_exp[0], r.f_exp[1] = s["f"]
-            d = 1.0 if D is None else complex(D[i])
+            d = s.get("D", 1.0) if D is None else complex(D[i])
             r.coef_re, r.coef_im = complex(d).real, complex(d).imag
         pref_lo, pref = prefactor
         pref = np.asarray(pref, dtype=complex)

@@ -5,6 +5,7 @@ import numpy as np
 
 from oracle import qmc as oq
 from oracle.decompose import decompose as odec
+from oracle.geometric import decompose as ogeo
 from paper_1508_02512_amd import frontend as fe
 from paper_1508_02512_amd import qmc
 from seeded_inputs.lattice import lattice
@@ -23,18 +24,23 @@ def ctx():
     return _CTX
 
 
-def gpu_plan(name, eps_hi=0, lam=0.0, r=2, ppl=0, precision=qmc.QMC_FP64):
-    secs, info = fe.decompose(PROBLEMS[name])
+def oracle_sectors(name, strategy="iterated"):
+    return (ogeo if strategy == "geometric" else odec)(PROBLEMS[name])
+
+
+def gpu_plan(name, eps_hi=0, lam=0.0, r=2, ppl=0, precision=qmc.QMC_FP64,
+             strategy="iterated"):
+    secs, info = fe.decompose(PROBLEMS[name], strategy)
     plan = ctx().plan(fe.sector_arrays(secs, info), info, eps_hi,
                       fe.prefactor_series(info, 12), lam=lam, korobov_r=r,
                       points_per_lane=ppl, precision=precision)
     return plan, info
 
 
-def sample_sectors(name, per_class=8, kin=None):
+def sample_sectors(name, per_class=8, kin=None, strategy="iterated"):
     """All sectors with at most one pole plus up to `per_class` evenly spaced
     sectors of every higher pole count."""
-    osecs, _ = odec(PROBLEMS[name])
+    osecs, _ = oracle_sectors(name, strategy)
     poles = [sum(1 for a in s["a"] if a == -1) for s in osecs]
     out = [i for i, k in enumerate(poles) if k <= 1]
     for k in sorted(set(poles)):
@@ -47,17 +53,18 @@ def sample_sectors(name, per_class=8, kin=None):
 
 
 def compare_sectors(name, kin, n, m, eps_hi=0, lam=0.0, r=2, ppl=0, tol=1e-12,
-                    sectors=None, seed=0, quad_from=2, precision=qmc.QMC_FP64):
+                    sectors=None, seed=0, quad_from=2, precision=qmc.QMC_FP64,
+                    strategy="iterated"):
     """Max over (sector, shift, order) of |gpu - oracle| / sum|terms|.
 
     Sectors with at least `quad_from` poles are compared with the oracle's
     binary128 build: the mixed differences of Eq. 11 amplify the FP64
     oracle's own rounding beyond the parity bar there."""
-    plan, info = gpu_plan(name, eps_hi, lam, r, ppl, precision)
+    plan, info = gpu_plan(name, eps_hi, lam, r, ppl, precision, strategy)
     z = lattice(n)
     shifts = shift_table(seed, m, 8)
     res = plan.integrate(fe.kin_vector(info, kin), (n, z), shifts, sector_sums=True)
-    osecs, oinfo = odec(PROBLEMS[name])
+    osecs, oinfo = oracle_sectors(name, strategy)
     idx = range(len(osecs)) if sectors is None else sectors
     worst = 0.0
     for s in idx:
