@@ -85,7 +85,28 @@ def cpu_baseline(target_seconds):
         if time.perf_counter() - t0 > target_seconds:
             break
     dt = time.perf_counter() - t0
+    # one thread, on a fifth of the time budget
+    ev1, done1, t1 = 0, 0, time.perf_counter()
+    for ns in nums:
+        oq.sector_sums(ns, n, z, sh, 2, 0.0, -4, 5, nthreads=1)
+        ev1 += n * m
+        done1 += 1
+        if time.perf_counter() - t1 > target_seconds / 5:
+            break
+    dt1 = time.perf_counter() - t1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": evals / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": ev1 / dt1,
+            "single_thread_sample": f"first {done1} sectors, same n and m, 1 thread",
+            "cpu_model": model,
             "sample": f"planar double box s=-3 t=-1, first {done} of {len(nums)} sectors, "
                       f"n={n}, m={m} shifts, FP64 oracle, {cores} threads"}
 
@@ -383,6 +404,20 @@ def main():
         ttt_geo, _ = time_to_target(plang, "fp64, geometric sectors")
         if ttt_geo is not None:
             ttt_geo.update({"sectors": len(gsecs), "host_planning_seconds": plan_s})
+            # full-size steps over the geometric sectors (same n, m)
+            jg = plang.bind(kin, (n, lattice(n)), shift_table(0, m, 8))
+            jg.run()
+            jg.fetch()
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            for _ in range(args.steps):
+                jg.run()
+                rg = jg.fetch()
+            torch.cuda.synchronize()
+            wg = (time.perf_counter() - tg) / args.steps
+            ttt_geo["full_step"] = {"evals_per_s": rg["evals"] / wg, "ms_per_step": wg * 1e3,
+                                    "evals_per_step": rg["evals"]}
+            jg.close()
         plang.close()
 
     # FP32-evaluation mode on the same workload

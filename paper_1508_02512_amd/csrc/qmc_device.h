@@ -15,6 +15,7 @@
 #define QMC_KSMAX 4
 #define QMC_NMASK (1 << QMC_KSMAX)
 #define QMC_BLOCK 256
+#define QMC_PROG_MAX 7       // power factors per term in a term program word
 #define QMC_NO_INT (-1000000)
 
 struct qmc_sec_dev {
@@ -34,6 +35,8 @@ struct qmc_sec_dev {
     double u0, u1, f0, f1;
     int32_t u0i, f0i;        // u0, f0 as integers, or QMC_NO_INT
     double lambda;
+    int32_t lnmask;          // bit j: the real kernel needs ln t_j
+    int32_t pad;
 };
 
 struct qmc_lat_dev {         // lattice of one sector, components permuted
@@ -61,6 +64,7 @@ struct qmc_launch_args {
     const qmc_lat_dev *lat;  // [n_sectors]
     const uint32_t *texp;    // [n_terms] packed exponents of U and F terms
     const double *texpd;     // [n_terms][QMC_DMAX] the same exponents as doubles
+    const uint32_t *tprog;   // [n_terms] each term as a list of power factors
     const double *tcoef;     // [n_points][n_terms] coefficients at each point
     const uint32_t *dexp;    // [n_dterms] packed exponents of derivative terms
     const double *dcoef;     // [n_points][n_dterms]

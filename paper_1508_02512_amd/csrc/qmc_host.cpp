@@ -147,6 +147,28 @@ static uint32_t pack_exps(const uint8_t *e, const int *perm, int dim)
     return p;
 }
 
+// A term prod_j t_j^e_j as a product of at most QMC_PROG_MAX factors taken
+// from the per-lane power table of the real kernel: slot 2 j holds t_j and
+// slot 2 j + 1 holds t_j^2, so e_j contributes e_j / 2 factors t_j^2 and one
+// t_j if e_j is odd.  Word layout: slots in bits 4k..4k+3, the factor count
+// in bits 28-30; bit 31 set means too many factors (the kernel then uses
+// exp(sum_j e_j ln t_j) instead).
+static uint32_t term_program(uint32_t packed)
+{
+    uint32_t w = 0;
+    int cnt = 0;
+    for (int j = 0; j < QMC_DMAX; ++j) {
+        const uint32_t e = (packed >> (4 * j)) & 15u;
+        for (uint32_t k = 0; k < e / 2 + (e & 1u); ++k) {
+            if (cnt == QMC_PROG_MAX) return 1u << 31;
+            const uint32_t slot = 2u * (uint32_t)j + (k < e / 2 ? 1u : 0u);
+            w |= slot << (4 * cnt);
+            ++cnt;
+        }
+    }
+    return w | ((uint32_t)cnt << 28);
+}
+
 // Algorithmic FP64 flops of one lattice point of one sector (see DESIGN
 // notes in the library documentation): add/sub/mul = 1, fma = 2, division
 // and each log/exp/atan = 20.
@@ -342,6 +364,7 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
             for (auto &pr : order) {
                 const uint8_t *e = P.exps + (size_t)pr.second * S.dim;
                 plan->texp.push_back(pack_exps(e, perm, S.dim));
+                if (term_program(plan->texp.back()) >> 31) h.mono_log = true;
                 const double *c = P.coef + (size_t)pr.second * pb->n_inv;
                 plan->tcoef_rows.insert(plan->tcoef_rows.end(), c, c + pb->n_inv);
                 int nnz = 0;
@@ -417,11 +440,16 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
     if (rc == QMC_OK && !plan->dexp.empty())
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
     std::vector<double> texpd(plan->texp.size() * QMC_DMAX);
-    for (size_t t = 0; t < plan->texp.size(); ++t)
+    std::vector<uint32_t> tprog(plan->texp.size());
+    for (size_t t = 0; t < plan->texp.size(); ++t) {
         for (int j = 0; j < QMC_DMAX; ++j)
             texpd[t * QMC_DMAX + j] = (double)((plan->texp[t] >> (4 * j)) & 15u);
+        tprog[t] = term_program(plan->texp[t]);
+    }
     if (rc == QMC_OK)
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_texpd, sizeof(double) * texpd.size());
+    if (rc == QMC_OK)
+        rc = qmc_dev_alloc(ctx, (void **)&plan->d_tprog, sizeof(uint32_t) * tprog.size());
     if (rc != QMC_OK) {
         qmc_plan_free(plan);
         return rc;
@@ -436,6 +464,9 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(plan->d_texpd, texpd.data(), sizeof(double) * texpd.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(plan->d_tprog, tprog.data(), sizeof(uint32_t) * tprog.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         qmc_plan_free(plan);
@@ -472,6 +503,11 @@ qmc_sec_dev qmc_sec_host::dev() const
     d.u0i = u0i;
     d.f0i = f0i;
     d.lambda = lambda;
+    // ln t_j feeds the pole variables, t_j^(b_j eps), non-integer powers
+    // t_j^a_j and the exp-form monomials; the others skip it
+    d.lnmask = 0;
+    for (int j = 0; j < dim; ++j)
+        if (mono_log || j < ks || b[j] != 0.0 || aint[j] == QMC_NO_INT) d.lnmask |= 1 << j;
     return d;
 }
 
@@ -482,6 +518,7 @@ extern "C" void qmc_plan_free(qmc_plan *plan)
     qmc_dev_free(ctx, plan->d_sec, sizeof(qmc_sec_dev) * plan->secs.size());
     qmc_dev_free(ctx, plan->d_texp, sizeof(uint32_t) * plan->texp.size());
     qmc_dev_free(ctx, plan->d_texpd, sizeof(double) * plan->texp.size() * QMC_DMAX);
+    qmc_dev_free(ctx, plan->d_tprog, sizeof(uint32_t) * plan->texp.size());
     qmc_dev_free(ctx, plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
     delete plan;
 }
@@ -798,6 +835,7 @@ extern "C" int qmc_run(qmc_job *job)
     A.lat = job->d_lat;
     A.texp = plan->d_texp;
     A.texpd = plan->d_texpd;
+    A.tprog = plan->d_tprog;
     A.tcoef = job->d_coef;
     A.dexp = plan->d_dexp;
     A.dcoef = job->d_dcoef;

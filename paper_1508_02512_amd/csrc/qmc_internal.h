@@ -53,6 +53,7 @@ struct qmc_sec_host {
     double u0 = 0, u1 = 0, f0 = 0, f1 = 0;
     int u0i = 0, f0i = 0;
     double lambda = 0.0;
+    bool mono_log = false;       // some term needs exp(sum_j e_j ln t_j)
     std::complex<double> D = 1.0;
     std::vector<int> term_nnz;   // non-zero exponents per term (U and F)
     std::vector<int> dterm_nnz;  // the same for the derivative terms
@@ -81,6 +82,7 @@ struct qmc_plan {
     qmc_sec_dev *d_sec = nullptr;
     uint32_t *d_texp = nullptr;
     double *d_texpd = nullptr;
+    uint32_t *d_tprog = nullptr;
     uint32_t *d_dexp = nullptr;
 };
 

@@ -9,6 +9,12 @@
 // scalar loops; each lane owns one lattice point at a time and walks the
 // tile with stride 256 by incremental modular addition.
 //
+// Monomials of U and F are products of powers: each lane writes t_j and
+// t_j^2 into its own column of a work-group LDS table, and the host gives
+// every term as a short list of table slots (one LDS read and one multiply
+// per factor, against ~30 VALU operations for exp(sum_j e_j ln t_j), which
+// remains the path for terms of very high degree).
+//
 // T is the evaluation type: double (QMC_FP64) or float (QMC_FP32_EVAL).
 // Lattice points, the shift and the accumulation are FP64 in both.
 #pragma once
@@ -57,6 +63,18 @@ __device__ __forceinline__ T tmono_log(cptr<double> e, const T *lt, int d)
     for (int j = 0; j < QMC_DMAX; ++j)
         if (j < d) x = fma(T(e[j]), lt[j], x);
     return qmc_math::ex(x);
+}
+
+// prod_j t_j^e_j as the product of the factors a term program word lists
+// (slots 2 j: t_j, 2 j + 1: t_j^2), read from this lane's column of the
+// work-group's power table (one LDS column per lane, stride QMC_BLOCK)
+template <typename T>
+__device__ __forceinline__ T tmono_lds(uint32_t w, const T *col)
+{
+    const int cnt = (int)((w >> 28) & 7u);
+    T v = 1;
+    for (int k = 0; k < cnt; ++k) v *= col[((w >> (4 * k)) & 15u) * QMC_BLOCK];
+    return v;
 }
 
 template <typename T>
@@ -271,7 +289,8 @@ __device__ __forceinline__ void mobius_series(cptr<qmc_sec_dev> S, Point<KS, K, 
 
 // One work item (a tile of one (point, sector, shift) group).
 template <int KS, int K, typename T>
-__device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, const int item_id)
+__device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, const int item_id,
+                                                   T *col)
 {
     const qmc_item it = load_item(A.items, item_id);
     cptr<qmc_sec_dev> S = ro(A.sec) + it.sector;
@@ -282,6 +301,7 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
     cptr<double> coef = ro(A.tcoef) + (size_t)it.point * A.n_terms;
     cptr<double> shift = ro(A.shifts) + it.shift * QMC_DMAX;
     cptr<double> texpd = ro(A.texpd);
+    cptr<uint32_t> tprog = ro(A.tprog);
     const int r = A.korobov_r;
 
     uint32_t l[QMC_DMAX], step[QMC_DMAX];
@@ -334,7 +354,7 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                         constexpr int pole_lim = KS;
                         const bool pole = j < pole_lim;
                         const T bj = T(S->b[j]);
-                        lt[j] = qmc_math::ln(t[j]);
+                        if (S->lnmask >> j & 1) lt[j] = qmc_math::ln(t[j]);
                         if (pole) {
                             const int jp = pole ? j : 0;
                             P.invt[jp] = mobius::rcp(t[j]);
@@ -353,14 +373,31 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                     }
                 }
                 P.LN = LN;
+                // this lane's powers t_j, t_j^2 for the term programs; only
+                // the lane itself reads its column, so no barrier is needed
+#pragma unroll
+                for (int j = 0; j < QMC_DMAX; ++j) {
+                    if (j < d) {
+                        col[(2 * j) * QMC_BLOCK] = t[j];
+                        col[(2 * j + 1) * QMC_BLOCK] = t[j] * t[j];
+                    }
+                }
                 // U and F: one pass over the terms grouped by pole mask
 #pragma unroll
                 for (int m = 0; m < (1 << KS); ++m) {
                     T su = 0, sf = 0;
-                    for (int q = S->um[m]; q < S->um[m + 1]; ++q)
-                        su = fma(T(coef[q]), tmono_log<T>(texpd + q * QMC_DMAX, lt, d), su);
-                    for (int q = S->fm[m]; q < S->fm[m + 1]; ++q)
-                        sf = fma(T(coef[q]), tmono_log<T>(texpd + q * QMC_DMAX, lt, d), sf);
+                    for (int q = S->um[m]; q < S->um[m + 1]; ++q) {
+                        const uint32_t w = tprog[q];
+                        const T mono = (w >> 31) ? tmono_log<T>(texpd + q * QMC_DMAX, lt, d)
+                                                 : tmono_lds<T>(w, col);
+                        su = fma(T(coef[q]), mono, su);
+                    }
+                    for (int q = S->fm[m]; q < S->fm[m + 1]; ++q) {
+                        const uint32_t w = tprog[q];
+                        const T mono = (w >> 31) ? tmono_log<T>(texpd + q * QMC_DMAX, lt, d)
+                                                 : tmono_lds<T>(w, col);
+                        sf = fma(T(coef[q]), mono, sf);
+                    }
                     P.SU[m] = su;
                     P.SF[m] = sf;
                 }
@@ -409,6 +446,7 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
 // Minimum waves per SIMD the register allocator must allow, i.e. how far
 // it spills to buy occupancy.  Chosen per class from sweeps on the planar
 // double box (n = 1000003, 4 shifts, ms per launch, FP64 / FP32):
+//   poles 0: 4 waves (5.1 vs 6.1 ms at 3) / unconstrained
 //   poles 1: 4 waves (41.3 vs 47.9 ms) / unconstrained
 //   poles 2: 3 (80.8 vs 105.3; 4 waves, 77.4 ms, spill 39 VGPRs and write
 //            ~390 GB of scratch to HBM per launch) / 6 (45.7 vs 58.7)
@@ -417,7 +455,7 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
 template <int KS, typename T>
 constexpr int min_waves()
 {
-    if (sizeof(T) == 8) return KS == 1 ? 4 : (KS == 2 || KS == 3 ? 3 : 2);
+    if (sizeof(T) == 8) return KS <= 1 ? 4 : (KS == 2 || KS == 3 ? 3 : 2);
     return KS <= 1 ? 1 : (KS == 2 ? 6 : (KS == 3 ? 4 : 3));
 }
 
@@ -425,8 +463,10 @@ template <int KS, int K, typename T>
 __global__ __launch_bounds__(QMC_BLOCK)
 __attribute__((amdgpu_waves_per_eu(min_waves<KS, T>(), 8))) void qmc_eval_real(qmc_launch_args A)
 {
+    // per-lane power table: slot s of lane x at pw[s * QMC_BLOCK + x]
+    __shared__ T pw[2 * QMC_DMAX * QMC_BLOCK];
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
-        qmc_eval_real_item<KS, K, T>(A, item);
+        qmc_eval_real_item<KS, K, T>(A, item, pw + threadIdx.x);
         __syncthreads();
     }
 }

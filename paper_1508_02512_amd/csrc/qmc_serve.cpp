@@ -303,6 +303,7 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act)
         A.lat = (const qmc_lat_dev *)d_lat + B.lat_off;
         A.texp = P->d_texp;
         A.texpd = P->d_texpd;
+        A.tprog = P->d_tprog;
         A.tcoef = (const double *)d_coef + B.coef_off;
         A.dexp = P->d_dexp;
         A.dcoef = (const double *)d_dcoef + B.dcoef_off;
