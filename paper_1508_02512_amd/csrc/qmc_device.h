@@ -15,7 +15,7 @@
 #define QMC_KSMAX 4
 #define QMC_NMASK (1 << QMC_KSMAX)
 #define QMC_BLOCK 256
-#define QMC_PROG_MAX 7       // power factors per term in a term program word
+#define QMC_PROG_SLOTS 17    // power table slots: t_j, t_j^2 (j < 8) and 1
 #define QMC_NO_INT (-1000000)
 
 struct qmc_sec_dev {
@@ -64,7 +64,7 @@ struct qmc_launch_args {
     const qmc_lat_dev *lat;  // [n_sectors]
     const uint32_t *texp;    // [n_terms] packed exponents of U and F terms
     const double *texpd;     // [n_terms][QMC_DMAX] the same exponents as doubles
-    const uint32_t *tprog;   // [n_terms] each term as a list of power factors
+    const uint32_t *tprog;   // [n_terms][2] each term as two 4-factor words
     const double *tcoef;     // [n_points][n_terms] coefficients at each point
     const uint32_t *dexp;    // [n_dterms] packed exponents of derivative terms
     const double *dcoef;     // [n_points][n_dterms]

@@ -147,26 +147,30 @@ static uint32_t pack_exps(const uint8_t *e, const int *perm, int dim)
     return p;
 }
 
-// A term prod_j t_j^e_j as a product of at most QMC_PROG_MAX factors taken
-// from the per-lane power table of the real kernel: slot 2 j holds t_j and
-// slot 2 j + 1 holds t_j^2, so e_j contributes e_j / 2 factors t_j^2 and one
-// t_j if e_j is odd.  Word layout: slots in bits 4k..4k+3, the factor count
-// in bits 28-30; bit 31 set means too many factors (the kernel then uses
-// exp(sum_j e_j ln t_j) instead).
-static uint32_t term_program(uint32_t packed)
+// A term prod_j t_j^e_j as a product of factors taken from the per-lane
+// power table of the real kernel: slot 2 j holds t_j, slot 2 j + 1 holds
+// t_j^2 and slot 16 holds 1, so e_j contributes e_j / 2 factors t_j^2 and
+// one t_j if e_j is odd.  Two words of four 5-bit slots (bits 5k..5k+4),
+// unused slots 16; bit 30 of the first word: the second word is needed;
+// bit 31: more than 8 factors (the kernel then uses exp(sum_j e_j ln t_j)).
+static void term_program(uint32_t packed, uint32_t *w)
 {
-    uint32_t w = 0;
+    uint32_t slots[8];
     int cnt = 0;
+    w[0] = w[1] = 0;
     for (int j = 0; j < QMC_DMAX; ++j) {
         const uint32_t e = (packed >> (4 * j)) & 15u;
         for (uint32_t k = 0; k < e / 2 + (e & 1u); ++k) {
-            if (cnt == QMC_PROG_MAX) return 1u << 31;
-            const uint32_t slot = 2u * (uint32_t)j + (k < e / 2 ? 1u : 0u);
-            w |= slot << (4 * cnt);
-            ++cnt;
+            if (cnt == 8) {
+                w[0] = 1u << 31;
+                return;
+            }
+            slots[cnt++] = 2u * (uint32_t)j + (k < e / 2 ? 1u : 0u);
         }
     }
-    return w | ((uint32_t)cnt << 28);
+    for (int k = 0; k < 8; ++k)
+        w[k / 4] |= (k < cnt ? slots[k] : (uint32_t)(QMC_PROG_SLOTS - 1)) << (5 * (k % 4));
+    if (cnt > 4) w[0] |= 1u << 30;
 }
 
 // Algorithmic FP64 flops of one lattice point of one sector (see DESIGN
@@ -364,7 +368,9 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
             for (auto &pr : order) {
                 const uint8_t *e = P.exps + (size_t)pr.second * S.dim;
                 plan->texp.push_back(pack_exps(e, perm, S.dim));
-                if (term_program(plan->texp.back()) >> 31) h.mono_log = true;
+                uint32_t w[2];
+                term_program(plan->texp.back(), w);
+                if (w[0] >> 31) h.mono_log = true;
                 const double *c = P.coef + (size_t)pr.second * pb->n_inv;
                 plan->tcoef_rows.insert(plan->tcoef_rows.end(), c, c + pb->n_inv);
                 int nnz = 0;
@@ -440,11 +446,11 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
     if (rc == QMC_OK && !plan->dexp.empty())
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
     std::vector<double> texpd(plan->texp.size() * QMC_DMAX);
-    std::vector<uint32_t> tprog(plan->texp.size());
+    std::vector<uint32_t> tprog(plan->texp.size() * 2);
     for (size_t t = 0; t < plan->texp.size(); ++t) {
         for (int j = 0; j < QMC_DMAX; ++j)
             texpd[t * QMC_DMAX + j] = (double)((plan->texp[t] >> (4 * j)) & 15u);
-        tprog[t] = term_program(plan->texp[t]);
+        term_program(plan->texp[t], &tprog[2 * t]);
     }
     if (rc == QMC_OK)
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_texpd, sizeof(double) * texpd.size());
@@ -518,7 +524,7 @@ extern "C" void qmc_plan_free(qmc_plan *plan)
     qmc_dev_free(ctx, plan->d_sec, sizeof(qmc_sec_dev) * plan->secs.size());
     qmc_dev_free(ctx, plan->d_texp, sizeof(uint32_t) * plan->texp.size());
     qmc_dev_free(ctx, plan->d_texpd, sizeof(double) * plan->texp.size() * QMC_DMAX);
-    qmc_dev_free(ctx, plan->d_tprog, sizeof(uint32_t) * plan->texp.size());
+    qmc_dev_free(ctx, plan->d_tprog, sizeof(uint32_t) * plan->texp.size() * 2);
     qmc_dev_free(ctx, plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
     delete plan;
 }

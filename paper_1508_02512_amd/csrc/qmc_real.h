@@ -11,9 +11,9 @@
 //
 // Monomials of U and F are products of powers: each lane writes t_j and
 // t_j^2 into its own column of a work-group LDS table, and the host gives
-// every term as a short list of table slots (one LDS read and one multiply
-// per factor, against ~30 VALU operations for exp(sum_j e_j ln t_j), which
-// remains the path for terms of very high degree).
+// every term as words of four table slots (independent LDS reads and a
+// product tree, against ~30 VALU operations for exp(sum_j e_j ln t_j),
+// which remains the path for terms of very high degree).
 //
 // T is the evaluation type: double (QMC_FP64) or float (QMC_FP32_EVAL).
 // Lattice points, the shift and the accumulation are FP64 in both.
@@ -65,15 +65,26 @@ __device__ __forceinline__ T tmono_log(cptr<double> e, const T *lt, int d)
     return qmc_math::ex(x);
 }
 
-// prod_j t_j^e_j as the product of the factors a term program word lists
-// (slots 2 j: t_j, 2 j + 1: t_j^2), read from this lane's column of the
-// work-group's power table (one LDS column per lane, stride QMC_BLOCK)
+// Product of the four power-table factors a term program word lists
+// (slots 2 j: t_j, 2 j + 1: t_j^2, 16: 1), read from this lane's column of
+// the work-group's power table (stride QMC_BLOCK).  The four reads are
+// independent, so their LDS latencies overlap.
 template <typename T>
-__device__ __forceinline__ T tmono_lds(uint32_t w, const T *col)
+__device__ __forceinline__ T prod4(uint32_t w, const T *col)
 {
-    const int cnt = (int)((w >> 28) & 7u);
-    T v = 1;
-    for (int k = 0; k < cnt; ++k) v *= col[((w >> (4 * k)) & 15u) * QMC_BLOCK];
+    const T a = col[(w & 31u) * QMC_BLOCK];
+    const T b = col[((w >> 5) & 31u) * QMC_BLOCK];
+    const T c = col[((w >> 10) & 31u) * QMC_BLOCK];
+    const T e = col[((w >> 15) & 31u) * QMC_BLOCK];
+    return (a * b) * (c * e);
+}
+
+template <typename T>
+__device__ __forceinline__ T tmono_lds(cptr<uint32_t> w, const T *col)
+{
+    const uint32_t w0 = w[0];
+    T v = prod4<T>(w0, col);
+    if (w0 >> 30 & 1u) v *= prod4<T>(w[1], col);
     return v;
 }
 
@@ -387,15 +398,15 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                 for (int m = 0; m < (1 << KS); ++m) {
                     T su = 0, sf = 0;
                     for (int q = S->um[m]; q < S->um[m + 1]; ++q) {
-                        const uint32_t w = tprog[q];
-                        const T mono = (w >> 31) ? tmono_log<T>(texpd + q * QMC_DMAX, lt, d)
-                                                 : tmono_lds<T>(w, col);
+                        const T mono = (tprog[2 * q] >> 31)
+                                           ? tmono_log<T>(texpd + q * QMC_DMAX, lt, d)
+                                           : tmono_lds<T>(tprog + 2 * q, col);
                         su = fma(T(coef[q]), mono, su);
                     }
                     for (int q = S->fm[m]; q < S->fm[m + 1]; ++q) {
-                        const uint32_t w = tprog[q];
-                        const T mono = (w >> 31) ? tmono_log<T>(texpd + q * QMC_DMAX, lt, d)
-                                                 : tmono_lds<T>(w, col);
+                        const T mono = (tprog[2 * q] >> 31)
+                                           ? tmono_log<T>(texpd + q * QMC_DMAX, lt, d)
+                                           : tmono_lds<T>(tprog + 2 * q, col);
                         sf = fma(T(coef[q]), mono, sf);
                     }
                     P.SU[m] = su;
@@ -448,14 +459,15 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
 // double box (n = 1000003, 4 shifts, ms per launch, FP64 / FP32):
 //   poles 0: 4 waves (5.1 vs 6.1 ms at 3) / unconstrained
 //   poles 1: 4 waves (41.3 vs 47.9 ms) / unconstrained
-//   poles 2: 3 (80.8 vs 105.3; 4 waves, 77.4 ms, spill 39 VGPRs and write
-//            ~390 GB of scratch to HBM per launch) / 6 (45.7 vs 58.7)
+//   poles 2: 4 (57.7 vs 64.7 at 3 with the LDS power table; with exp-form
+//            monomials 4 waves spilled 39 VGPRs and wrote ~390 GB of
+//            scratch per launch) / 6 (45.7 vs 58.7)
 //   poles 3: 3 (99.2; 2 gives 116.6, 4 gives 106.4) / 4 (73.3 vs 88.6)
 //   poles 4: 2 (103.1; 1 gives 161.6, 3 gives 115.1) / 3 (82.2 vs 103.0)
 template <int KS, typename T>
 constexpr int min_waves()
 {
-    if (sizeof(T) == 8) return KS <= 1 ? 4 : (KS == 2 || KS == 3 ? 3 : 2);
+    if (sizeof(T) == 8) return KS <= 2 ? 4 : (KS == 3 ? 3 : 2);
     return KS <= 1 ? 1 : (KS == 2 ? 6 : (KS == 3 ? 4 : 3));
 }
 
@@ -463,8 +475,10 @@ template <int KS, int K, typename T>
 __global__ __launch_bounds__(QMC_BLOCK)
 __attribute__((amdgpu_waves_per_eu(min_waves<KS, T>(), 8))) void qmc_eval_real(qmc_launch_args A)
 {
-    // per-lane power table: slot s of lane x at pw[s * QMC_BLOCK + x]
-    __shared__ T pw[2 * QMC_DMAX * QMC_BLOCK];
+    // per-lane power table: slot s of lane x at pw[s * QMC_BLOCK + x]; the
+    // last slot is the constant 1 that pads the term programs
+    __shared__ T pw[QMC_PROG_SLOTS * QMC_BLOCK];
+    pw[(QMC_PROG_SLOTS - 1) * QMC_BLOCK + threadIdx.x] = T(1);
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
         qmc_eval_real_item<KS, K, T>(A, item, pw + threadIdx.x);
         __syncthreads();
