@@ -177,4 +177,27 @@ __device__ __forceinline__ void store_violations(int viol, int32_t *dst)
     if (threadIdx.x == 0) *dst = vsum;
 }
 
+// Product of the four power-table factors a term program word lists
+// (slots 2 j: t_j, 2 j + 1: t_j^2, 16: 1), read from this lane's column of
+// the work-group's power table (stride QMC_BLOCK).  The four reads are
+// independent, so their LDS latencies overlap.
+template <typename T>
+__device__ __forceinline__ T prod4(uint32_t w, const T *col)
+{
+    const T a = col[(w & 31u) * QMC_BLOCK];
+    const T b = col[((w >> 5) & 31u) * QMC_BLOCK];
+    const T c = col[((w >> 10) & 31u) * QMC_BLOCK];
+    const T e = col[((w >> 15) & 31u) * QMC_BLOCK];
+    return (a * b) * (c * e);
+}
+
+template <typename T>
+__device__ __forceinline__ T tmono_lds(cptr<uint32_t> w, const T *col)
+{
+    const uint32_t w0 = w[0];
+    T v = prod4<T>(w0, col);
+    if (w0 >> 30 & 1u) v *= prod4<T>(w[1], col);
+    return v;
+}
+
 } // namespace qmc

@@ -109,6 +109,18 @@ __device__ __forceinline__ double rmonomial(uint32_t e, const double *t)
 }
 
 template <int DM, int KS, int K>
+struct CplxPoint;
+
+// derivative term q at the corner's real point: power-table product, or the
+// branchy product of powers for terms with more than eight factors
+template <int DM, int KS, int K>
+__device__ __forceinline__ double dmono(const CplxPoint<DM, KS, K> &P, int q, const double *tp)
+{
+    return (P.dprog[2 * q] >> 31) ? rmonomial<DM>(P.dexp[q], tp)
+                                  : tmono_lds<double>(P.dprog + 2 * q, P.col);
+}
+
+template <int DM, int KS, int K>
 struct CplxPoint {
     double t[DM], omt[DM], lt[DM];
     double invt[KS > 0 ? KS : 1];
@@ -117,6 +129,8 @@ struct CplxPoint {
     cptr<double> coef;               // U, F coefficients at this point
     cptr<double> dcoef;              // derivative coefficients at this point
     cptr<uint32_t> texp, dexp;
+    cptr<uint32_t> dprog;            // derivative terms as power-table words
+    double *col;                     // this lane's column of the power table
     double lam;                      // deformation parameter of this sector and point
     int bad;
 };
@@ -135,6 +149,15 @@ __device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &
     }
     const int d = S->dim;
     const double lam = P.lam;
+    // powers of this corner's real point for the derivative terms (only
+    // the lane itself reads its column)
+#pragma unroll
+    for (int j = 0; j < DM; ++j) {
+        if (j < d) {
+            P.col[(2 * j) * QMC_BLOCK] = tp[j];
+            P.col[(2 * j + 1) * QMC_BLOCK] = tp[j] * tp[j];
+        }
+    }
     // gradient of F at the real point
     double g[DM];
 #pragma unroll
@@ -142,7 +165,7 @@ __device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &
         double s = 0.0;
         if (j < d)
             for (int q = S->d1[j]; q < S->d1[j + 1]; ++q)
-                s = fma(P.dcoef[q], rmonomial<DM>(P.dexp[q], tp), s);
+                s = fma(P.dcoef[q], dmono<DM>(P, q, tp), s);
         g[j] = s;
     }
     // q_j = lambda (1 - t_j) g_j, phi_j = 1 - i q_j, z_j = t_j phi_j
@@ -174,7 +197,7 @@ __device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &
             if (j < d) {
                 const int idx = k * QMC_DMAX - k * (k - 1) / 2 + (j - k);
                 for (int q = S->d2[idx]; q < S->d2[idx + 1]; ++q)
-                    hs = fma(P.dcoef[q], rmonomial<DM>(P.dexp[q], tp), hs);
+                    hs = fma(P.dcoef[q], dmono<DM>(P, q, tp), hs);
             }
             double a = -(sj[j] * hs) * sj[k];
             if (j == k && j < d) a -= lam * (op[j] - tp[j]) * g[j];
@@ -290,7 +313,8 @@ __device__ __forceinline__ void corners_folded(cptr<qmc_sec_dev> S, CplxPoint<DM
 
 // One work item (a tile of one (point, sector, shift) group).
 template <int DM, int KS, int K>
-__device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, const int item_id)
+__device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, const int item_id,
+                                                   double *col)
 {
     const qmc_item it = load_item(A.items, item_id);
     cptr<qmc_sec_dev> S = ro(A.sec) + it.sector;
@@ -329,6 +353,8 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
             P.dcoef = ro(A.dcoef) + (size_t)it.point * A.n_dterms;
             P.texp = ro(A.texp);
             P.dexp = ro(A.dexp);
+            P.dprog = ro(A.dprog);
+            P.col = col;
             P.lam = ro(A.lam)[(size_t)it.point * A.n_sec + it.sector];
             P.bad = 0;
             double w = 1.0;
@@ -403,6 +429,12 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
 // per work-group when the grid covers the list, a persistent loop when the
 // grid is smaller.  Each item writes only its own slot, so the result does
 // not depend on the grid.
+// The derivative terms (gradient and Hessian of F at each corner's real
+// point) are products from a per-lane LDS power table, as in the real
+// kernel; this cut the gg -> HH double boxes by 1.4x and the non-planar
+// vertex by 1.5x against the branchy product of powers, which remains
+// for the complex monomials of U and F (their table would not fit beside
+// four work-groups per CU).
 // The deformed integrand is bound by scalar work (wave-uniform term loops
 // and exponent decoding) and its latency, so it is built for four waves per
 // SIMD, which lets one wave's scalar and another's vector instructions issue
@@ -414,8 +446,12 @@ template <int DM, int KS, int K>
 __global__ __launch_bounds__(QMC_BLOCK)
 __attribute__((amdgpu_waves_per_eu(4, 8))) void qmc_eval_cplx(qmc_launch_args A)
 {
+    // per-lane power table of the corner points (slot layout as in the
+    // real kernel, last slot the constant 1)
+    __shared__ double pw[QMC_PROG_SLOTS * QMC_BLOCK];
+    pw[(QMC_PROG_SLOTS - 1) * QMC_BLOCK + threadIdx.x] = 1.0;
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
-        qmc_eval_cplx_item<DM, KS, K>(A, item);
+        qmc_eval_cplx_item<DM, KS, K>(A, item, pw + threadIdx.x);
         __syncthreads();
     }
 }

@@ -65,6 +65,7 @@ struct qmc_launch_args {
     const uint32_t *texp;    // [n_terms] packed exponents of U and F terms
     const double *texpd;     // [n_terms][QMC_DMAX] the same exponents as doubles
     const uint32_t *tprog;   // [n_terms][2] each term as two 4-factor words
+    const uint32_t *dprog;   // [n_dterms][2] the same for the derivative terms
     const double *tcoef;     // [n_points][n_terms] coefficients at each point
     const uint32_t *dexp;    // [n_dterms] packed exponents of derivative terms
     const double *dcoef;     // [n_points][n_dterms]

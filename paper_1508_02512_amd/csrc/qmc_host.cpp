@@ -456,6 +456,10 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_texpd, sizeof(double) * texpd.size());
     if (rc == QMC_OK)
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_tprog, sizeof(uint32_t) * tprog.size());
+    std::vector<uint32_t> dprog(plan->dexp.size() * 2);
+    for (size_t t = 0; t < plan->dexp.size(); ++t) term_program(plan->dexp[t], &dprog[2 * t]);
+    if (rc == QMC_OK && !dprog.empty())
+        rc = qmc_dev_alloc(ctx, (void **)&plan->d_dprog, sizeof(uint32_t) * dprog.size());
     if (rc != QMC_OK) {
         qmc_plan_free(plan);
         return rc;
@@ -473,6 +477,9 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(plan->d_tprog, tprog.data(), sizeof(uint32_t) * tprog.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !dprog.empty())
+        e = hipMemcpy(plan->d_dprog, dprog.data(), sizeof(uint32_t) * dprog.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         qmc_plan_free(plan);
@@ -525,6 +532,7 @@ extern "C" void qmc_plan_free(qmc_plan *plan)
     qmc_dev_free(ctx, plan->d_texp, sizeof(uint32_t) * plan->texp.size());
     qmc_dev_free(ctx, plan->d_texpd, sizeof(double) * plan->texp.size() * QMC_DMAX);
     qmc_dev_free(ctx, plan->d_tprog, sizeof(uint32_t) * plan->texp.size() * 2);
+    qmc_dev_free(ctx, plan->d_dprog, sizeof(uint32_t) * plan->dexp.size() * 2);
     qmc_dev_free(ctx, plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
     delete plan;
 }
@@ -842,6 +850,7 @@ extern "C" int qmc_run(qmc_job *job)
     A.texp = plan->d_texp;
     A.texpd = plan->d_texpd;
     A.tprog = plan->d_tprog;
+    A.dprog = plan->d_dprog;
     A.tcoef = job->d_coef;
     A.dexp = plan->d_dexp;
     A.dcoef = job->d_dcoef;

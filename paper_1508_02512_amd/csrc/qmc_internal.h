@@ -83,6 +83,7 @@ struct qmc_plan {
     uint32_t *d_texp = nullptr;
     double *d_texpd = nullptr;
     uint32_t *d_tprog = nullptr;
+    uint32_t *d_dprog = nullptr;
     uint32_t *d_dexp = nullptr;
 };
 

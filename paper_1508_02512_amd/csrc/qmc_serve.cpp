@@ -304,6 +304,7 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act)
         A.texp = P->d_texp;
         A.texpd = P->d_texpd;
         A.tprog = P->d_tprog;
+        A.dprog = P->d_dprog;
         A.tcoef = (const double *)d_coef + B.coef_off;
         A.dexp = P->d_dexp;
         A.dcoef = (const double *)d_dcoef + B.dcoef_off;
