@@ -35,7 +35,7 @@ DOUBLING_PRIMES = [4099, 10007, 65521, 131071, 262139, 524287, 1048573, 2097143,
 # FETCH_SIZE and WRITE_SIZE passes calibrated with a 256 MiB copy (recorded
 # in profiles/qmc_eval_real_doublebox_n1000003_counters.md).  A class absent
 # here was not measured with the current kernel and reports null.
-TRAFFIC_BYTES = {(4, 0, 1000003, 16): 224.85e9, (3, 0, 1000003, 16): 112.5e6}
+TRAFFIC_BYTES = {(4, 0, 1000003, 16): 220.18e9, (3, 0, 1000003, 16): 8.080e9}
 
 
 def parse():
