@@ -156,3 +156,42 @@ def test_double_box_benchmark_config_sampled():
         scale = abss[..., 0] + abss[..., 1]
         assert np.all(np.abs(gpu - sums) <= 1e-12 * scale), s
     plan.close()
+
+
+def test_term_program_paths():
+    """Synthetic three-variable sectors whose U and F terms take every
+    monomial path of the real kernel: one power-table word (<= 4 factors),
+    two words (5-8 factors), the exp(sum e_j ln t_j) form (> 8 factors,
+    exponents up to 15), a non-integer a_j, and a pole on the Moebius path."""
+    from fractions import Fraction as Fr
+
+    U = {(0, 0, 0): 1.0, (9, 1, 0): 2.0, (0, 2, 15): 1.0}      # 6 and 9 factors
+    F = {(0, 0, 0): 3.0, (1, 1, 1): 1.0, (15, 15, 0): 0.5, (0, 0, 4): 1.0}
+    specs = [([0.0, 1.0, 0.5], [0.3, 0.0, 0.0]),                # no pole
+             ([-1.0, 0.0, 0.0], [-1.5, 0.2, 0.0])]              # one pole
+    u, f = (1.0, 1.0), (-2.0, -1.0)
+    arrs, osecs = [], []
+    for a, b in specs:
+        EU = np.array(sorted(U), dtype=np.uint8)
+        EF = np.array(sorted(F), dtype=np.uint8)
+        arrs.append({"dim": 3, "a": np.array(a), "b": np.array(b),
+                     "EU": EU, "CU": np.array([[U[tuple(e)]] for e in EU.tolist()]),
+                     "EF": EF, "CF": np.array([[F[tuple(e)]] for e in EF.tolist()]),
+                     "u": u, "f": f, "D": 1.0})
+        osecs.append({"a": [Fr(x) for x in a], "b": [Fr(x) for x in b],
+                      "U": {e: {"1": Fr(c)} for e, c in U.items()},
+                      "F": {e: {"1": Fr(c)} for e, c in F.items()}})
+    info = {"invariants": ["1"]}
+    oinfo = {"u0": Fr(1), "u1": Fr(1), "f0": Fr(-2), "f1": Fr(-1)}
+    plan = ctx().plan(arrs, info, 0, (0, np.array([1.0 + 0j])))
+    n, z, sh = 10007, lattice(10007), shift_table(5, 3, 8)
+    res = plan.integrate(np.array([[1.0]]), (n, z), sh, sector_sums=True)
+    for s in range(2):
+        ns = oq.NumericSector(osecs[s], oinfo, {})
+        sums, abss, _ = oq.sector_sums(ns, n, z, sh, 2, 0.0, res["sec_lo"],
+                                       plan.info.sec_orders)
+        gpu = res["sector_sums"][0, s]
+        scale = abss[..., 0] + abss[..., 1]
+        assert np.all(np.abs(gpu - sums) <= 1e-12 * scale), s
+        assert np.all(np.abs(sums[:, -1]) > 0)
+    plan.close()
