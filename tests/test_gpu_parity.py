@@ -124,6 +124,33 @@ def test_invalid_inputs_raise():
     assert e.value.code == -3
 
 
+def test_degenerate_and_oversized_inputs_raise():
+    """Empty kinematics, a one-point lattice, and sectors beyond the
+    library's limits (9 variables, 5 poles, an exponent of 16) are refused
+    before any kernel runs."""
+    from paper_1508_02512_amd import qmc
+    plan, info = gpu_plan("box")
+    kin = fe.kin_vector(info, {"s": -3.0, "t": -2.0})
+    with pytest.raises(qmc.QMCError):           # no kinematic point
+        plan.integrate(np.zeros((0, kin.shape[0])), (1009, lattice(1009)), shift_table(0, 2, 8))
+    with pytest.raises(qmc.QMCError):           # n = 1
+        plan.integrate(kin, (1, lattice(1009)), shift_table(0, 2, 8))
+    plan.close()
+    one = {(0,) * 9: 1.0, (1,) + (0,) * 8: 1.0}
+    arrs, _, _ = _synthetic(one, one, [([0.0] * 9, [0.0] * 9)], (1.0, 0.0), (-1.0, 0.0))
+    with pytest.raises(qmc.QMCError):           # 9 variables
+        ctx().plan(arrs, {"invariants": ["1"]}, 0, (0, np.array([1.0 + 0j])))
+    one = {(0,) * 5: 1.0, (1, 1, 1, 1, 1): 1.0}
+    arrs, _, _ = _synthetic(one, one, [([-1.0] * 5, [-1.0] * 5)], (1.0, 0.0), (-1.0, 0.0))
+    with pytest.raises(qmc.QMCError) as e:      # 5 poles
+        ctx().plan(arrs, {"invariants": ["1"]}, 0, (0, np.array([1.0 + 0j])))
+    assert e.value.code == -3
+    big = {(0, 0): 1.0, (16, 0): 1.0}
+    arrs, _, _ = _synthetic(big, big, [([0.0, 0.0], [0.0, 0.0])], (1.0, 0.0), (-1.0, 0.0))
+    with pytest.raises(qmc.QMCError):           # exponent 16 > QMC_MAX_EXP
+        ctx().plan(arrs, {"invariants": ["1"]}, 0, (0, np.array([1.0 + 0j])))
+
+
 def test_double_box_benchmark_config_sampled():
     """The benchmark workload itself: planar double box, all 882 sectors,
     n = 1000003, 16 shifts, in the launch shape bench.py times (automatic
@@ -158,40 +185,65 @@ def test_double_box_benchmark_config_sampled():
     plan.close()
 
 
-def test_term_program_paths():
-    """Synthetic three-variable sectors whose U and F terms take every
-    monomial path of the real kernel: one power-table word (<= 4 factors),
-    two words (5-8 factors), the exp(sum e_j ln t_j) form (> 8 factors,
-    exponents up to 15), a non-integer a_j, and a pole on the Moebius path."""
+def _synthetic(U, F, specs, u, f):
+    """GPU sector arrays and oracle sectors of hand-written sectors with
+    numeric coefficients (one invariant, the constant 1)."""
     from fractions import Fraction as Fr
 
-    U = {(0, 0, 0): 1.0, (9, 1, 0): 2.0, (0, 2, 15): 1.0}      # 6 and 9 factors
-    F = {(0, 0, 0): 3.0, (1, 1, 1): 1.0, (15, 15, 0): 0.5, (0, 0, 4): 1.0}
-    specs = [([0.0, 1.0, 0.5], [0.3, 0.0, 0.0]),                # no pole
-             ([-1.0, 0.0, 0.0], [-1.5, 0.2, 0.0])]              # one pole
-    u, f = (1.0, 1.0), (-2.0, -1.0)
     arrs, osecs = [], []
     for a, b in specs:
-        EU = np.array(sorted(U), dtype=np.uint8)
-        EF = np.array(sorted(F), dtype=np.uint8)
-        arrs.append({"dim": 3, "a": np.array(a), "b": np.array(b),
+        d = len(a)
+        EU = np.array(sorted(U), dtype=np.uint8).reshape(-1, d)
+        EF = np.array(sorted(F), dtype=np.uint8).reshape(-1, d)
+        arrs.append({"dim": d, "a": np.array(a, dtype=float), "b": np.array(b, dtype=float),
                      "EU": EU, "CU": np.array([[U[tuple(e)]] for e in EU.tolist()]),
                      "EF": EF, "CF": np.array([[F[tuple(e)]] for e in EF.tolist()]),
                      "u": u, "f": f, "D": 1.0})
         osecs.append({"a": [Fr(x) for x in a], "b": [Fr(x) for x in b],
                       "U": {e: {"1": Fr(c)} for e, c in U.items()},
                       "F": {e: {"1": Fr(c)} for e, c in F.items()}})
-    info = {"invariants": ["1"]}
-    oinfo = {"u0": Fr(1), "u1": Fr(1), "f0": Fr(-2), "f1": Fr(-1)}
-    plan = ctx().plan(arrs, info, 0, (0, np.array([1.0 + 0j])))
-    n, z, sh = 10007, lattice(10007), shift_table(5, 3, 8)
+    oinfo = {"u0": Fr(u[0]), "u1": Fr(u[1]), "f0": Fr(f[0]), "f1": Fr(f[1])}
+    return arrs, osecs, oinfo
+
+
+def _synthetic_parity(arrs, osecs, oinfo, n, m, quad_from=2):
+    plan = ctx().plan(arrs, {"invariants": ["1"]}, 0, (0, np.array([1.0 + 0j])))
+    z, sh = lattice(n), shift_table(5, m, 8)
     res = plan.integrate(np.array([[1.0]]), (n, z), sh, sector_sums=True)
-    for s in range(2):
+    for s in range(len(arrs)):
         ns = oq.NumericSector(osecs[s], oinfo, {})
         sums, abss, _ = oq.sector_sums(ns, n, z, sh, 2, 0.0, res["sec_lo"],
-                                       plan.info.sec_orders)
+                                       plan.info.sec_orders, quad=ns.nJ >= quad_from)
         gpu = res["sector_sums"][0, s]
         scale = abss[..., 0] + abss[..., 1]
         assert np.all(np.abs(gpu - sums) <= 1e-12 * scale), s
         assert np.all(np.abs(sums[:, -1]) > 0)
     plan.close()
+
+
+def test_largest_sector_shape():
+    """QMC_MAX_DIM = 8 variables with QMC_MAX_POLES = 4 poles (every power
+    table slot in use, the widest Moebius class) on a ragged lattice."""
+    U = {(0,) * 8: 1.0, (1, 0, 0, 0, 1, 0, 0, 0): 1.0, (0, 1, 0, 0, 0, 2, 0, 0): 0.5,
+         (0, 0, 1, 1, 0, 0, 1, 1): 2.0}
+    F = {(0,) * 8: 2.0, (1, 1, 0, 0, 0, 0, 0, 0): 1.0, (0, 0, 0, 2, 0, 0, 0, 1): 1.5,
+         (0, 0, 0, 0, 1, 1, 1, 0): 0.25, (0, 0, 0, 0, 0, 0, 0, 3): 1.0}
+    specs = [([-1.0, -1.0, -1.0, -1.0, 0.0, 1.0, 0.0, 2.0],
+              [-1.0, -0.5, -2.0, -1.5, 0.1, 0.0, 0.0, 0.3]),
+             ([0.0, 0.5, 1.0, 0.0, 0.0, 0.0, 3.0, 0.0],
+              [0.0, 0.0, 0.2, 0.0, 0.0, 0.0, 0.0, 0.0])]
+    print("synthetic dim 8, 4 poles, n=4099 m=2", flush=True)
+    _synthetic_parity(*_synthetic(U, F, specs, (1.0, 1.0), (-2.0, -1.0)), 4099, 2)
+
+
+def test_term_program_paths():
+    """Synthetic three-variable sectors whose U and F terms take every
+    monomial path of the real kernel: one power-table word (<= 4 factors),
+    two words (5-8 factors), the exp(sum e_j ln t_j) form (> 8 factors,
+    exponents up to 15), a non-integer a_j, and a pole on the Moebius path."""
+    U = {(0, 0, 0): 1.0, (9, 1, 0): 2.0, (0, 2, 15): 1.0}      # 6 and 9 factors
+    F = {(0, 0, 0): 3.0, (1, 1, 1): 1.0, (15, 15, 0): 0.5, (0, 0, 4): 1.0}
+    specs = [([0.0, 1.0, 0.5], [0.3, 0.0, 0.0]),                # no pole
+             ([-1.0, 0.0, 0.0], [-1.5, 0.2, 0.0])]              # one pole
+    print("synthetic term paths, n=10007 m=3", flush=True)
+    _synthetic_parity(*_synthetic(U, F, specs, (1.0, 1.0), (-2.0, -1.0)), 10007, 3)
