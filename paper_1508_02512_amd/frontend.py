@@ -14,9 +14,10 @@ per loop, D = 4 - 2 eps, so that
 with sum_j x_j (-q_j^2 + m_j^2) = -k^T M k + 2 k.Q + J, U = det M and
 F = adj(M)[Q, Q] + U J.
 
-Sector decomposition: primary sectors with x_l = 1 (Eqs. 3-6), then
-iterated splitting until U and F are monomial x (constant + higher terms)
-(Eqs. 7-8).  The split rule (the paper leaves it open) takes the first
+Sector decomposition: primary sectors with x_l = 1 (Eqs. 3-6), then either
+the geometric strategy the paper adopts (module ``geometric``: the normal
+fan of the Newton polytope of U F, fewest sectors) or iterated splitting
+until U and F are monomial x (constant + higher terms) (Eqs. 7-8).  The split rule (the paper leaves it open) takes the first
 polynomial without a constant term (U before F), its exponent vectors that
 no other exponent dominates componentwise, the closest pair (v, w) of them
 in the 1-norm (ties: lexicographically smallest, v < w), and splits on
