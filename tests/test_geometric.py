@@ -29,7 +29,8 @@ from seeded_inputs.lattice import lattice
 from seeded_inputs.problems import PROBLEMS
 from seeded_inputs.rng import shift_table
 
-ALL = ["box", "np_vertex", "triangle2l", "hh_box", "hh_planar", "hh_nonplanar",
+ALL = ["bubble", "bubble_massive", "triangle_offshell", "box", "np_vertex", "triangle2l",
+       "hh_box", "hh_planar", "hh_nonplanar",
        "doublebox", "doublebox_off14"]
 
 
