@@ -120,3 +120,20 @@ def test_lambda_backoff_recovers():
         qmc.submit(plan, kin, 1e-3, 1 << 12, 1 << 20, 8, 3, Z, lambda_halvings=17)
     plan.close()
     safe.close()
+
+
+def test_geometric_sectors_serve_the_table2_integral():
+    """I_C at the Table 2 point served from its 46 geometric sectors: the
+    request meets 1e-3 on every order without a lambda back-off, and its
+    result equals one pass of qmc_integrate over the same 2^k points."""
+    from seeded_inputs.problems import HH_POINT
+    print("serve: I_C geometric sectors", flush=True)
+    plan, info = gpu_plan("hh_planar", lam=1.0, strategy="geometric")
+    kin = fe.kin_vector(info, HH_POINT)
+    r = qmc.submit(plan, kin, 1e-3, 1 << 14, 1 << 22, 8, 3, Z, lambda_halvings=2).wait(300)
+    assert r["rc"] == 0 and r["lambda_halvings"] == 0
+    ref = plan.integrate(kin, (r["n_final"], Z), shift_table(3, 8, 8))
+    assert np.allclose(r["mean"], ref["mean"], rtol=1e-12, atol=1e-14)
+    rel = np.hypot(r["err_re"], r["err_im"]) / np.abs(r["mean"])
+    assert np.all(rel <= 1e-3)
+    plan.close()
