@@ -276,9 +276,35 @@ __device__ __forceinline__ void mobius_series(cptr<qmc_sec_dev> S, Point<KS, K, 
 // ---- kernel -------------------------------------------------------------
 
 // One work item (a tile of one (point, sector, shift) group).
+// The three- and four-pole FP64 classes run at three and two waves per
+// SIMD with more live values than registers.  Per-lane values that live
+// across the whole point loop but are touched once per point are kept in
+// LDS there instead, so the register allocator does not spill them to
+// scratch: the compensated sums (both classes; three poles only while
+// three work-groups still fit a CU's LDS) and the shift (four poles, where
+// only two work-groups share a CU and LDS has room for it).
+template <int KS, int K, typename T>
+constexpr bool lds_sums()
+{
+    return sizeof(T) == 8 && (KS == 4 || (KS == 3 && K <= 4));
+}
+
+template <int KS, typename T>
+constexpr bool lds_shift()
+{
+    return KS == 4 && sizeof(T) == 8;
+}
+
+template <int KS, int K, typename T>
+constexpr int lds_state_slots()
+{
+    constexpr int n = (lds_sums<KS, K, T>() ? 2 * K : 0) + (lds_shift<KS, T>() ? QMC_DMAX : 0);
+    return n > 0 ? n : 1;
+}
+
 template <int KS, int K, typename T>
 __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, const int item_id,
-                                                   T *col)
+                                                   T *col, double *st)
 {
     const qmc_item it = load_item(A.items, item_id);
     cptr<qmc_sec_dev> S = ro(A.sec) + it.sector;
@@ -292,6 +318,10 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
     cptr<uint32_t> tprog = ro(A.tprog);
     const int r = A.korobov_r;
 
+    constexpr bool LDS = lds_sums<KS, K, T>();
+    constexpr bool LDSH = lds_shift<KS, T>();
+    // LDS slots of this lane (stride QMC_BLOCK): sums 0..K-1, compensations
+    // K..2K-1, shift components 2K..2K+QMC_DMAX-1
     uint32_t l[QMC_DMAX], step[QMC_DMAX];
     double dl[QMC_DMAX];
 #pragma unroll
@@ -304,12 +334,16 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
             l[j] = (uint32_t)(((uint64_t)(it.start + it.stride * threadIdx.x) * z) % n);
             step[j] = (uint32_t)(((uint64_t)QMC_BLOCK * it.stride * z) % n);
             dl[j] = shift[S->perm[j]];
+            if constexpr (LDSH) st[(2 * K + j) * QMC_BLOCK] = dl[j];
         }
     }
 
     double acc[1][K], cmp[1][K];
 #pragma unroll
-    for (int q = 0; q < K; ++q) acc[0][q] = cmp[0][q] = 0.0;
+    for (int q = 0; q < K; ++q) {
+        acc[0][q] = cmp[0][q] = 0.0;
+        if constexpr (LDS) st[q * QMC_BLOCK] = st[(K + q) * QMC_BLOCK] = 0.0;
+    }
     int viol = 0;
 
     const int np = (int)((it.count + QMC_BLOCK - 1) / QMC_BLOCK);
@@ -322,7 +356,9 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
             for (int j = 0; j < QMC_DMAX; ++j) {
                 t[j] = 1;
                 if (j < d) {
-                    double y = fma((double)l[j], inv_n, dl[j]);
+                    double dj = dl[j];
+                    if constexpr (LDSH) dj = st[(2 * K + j) * QMC_BLOCK];
+                    double y = fma((double)l[j], inv_n, dj);
                     if (y >= 1.0) y -= 1.0;
                     T wj;
                     tkorobov<T>(r, T(y), T(1.0 - y), t[j], wj);
@@ -408,8 +444,19 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                     viol += 1;
                 } else {
                     const double wp = (double)(w * pn);
+                    if constexpr (LDS) {
 #pragma unroll
-                    for (int q = 0; q < K; ++q) neumaier(acc[0][q], cmp[0][q], wp * (double)g[q]);
+                        for (int q = 0; q < K; ++q) {
+                            double s = st[q * QMC_BLOCK], c = st[(K + q) * QMC_BLOCK];
+                            neumaier(s, c, wp * (double)g[q]);
+                            st[q * QMC_BLOCK] = s;
+                            st[(K + q) * QMC_BLOCK] = c;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < K; ++q)
+                            neumaier(acc[0][q], cmp[0][q], wp * (double)g[q]);
+                    }
                 }
             }
         }
@@ -422,6 +469,13 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
         }
     }
 
+    if constexpr (LDS) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            acc[0][q] = st[q * QMC_BLOCK];
+            cmp[0][q] = st[(K + q) * QMC_BLOCK];
+        }
+    }
     double *dst = A.partial + (size_t)item_id * A.kstride * 4;
     block_reduce_store<K, 1>(acc, cmp, dst, A.kstride);
     store_violations(viol, A.viol + item_id);
@@ -455,9 +509,10 @@ __attribute__((amdgpu_waves_per_eu(min_waves<KS, T>(), 8))) void qmc_eval_real(q
     // per-lane power table: slot s of lane x at pw[s * QMC_BLOCK + x]; the
     // last slot is the constant 1 that pads the term programs
     __shared__ T pw[QMC_PROG_SLOTS * QMC_BLOCK];
+    __shared__ double st[lds_state_slots<KS, K, T>() * QMC_BLOCK];
     pw[(QMC_PROG_SLOTS - 1) * QMC_BLOCK + threadIdx.x] = T(1);
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
-        qmc_eval_real_item<KS, K, T>(A, item, pw + threadIdx.x);
+        qmc_eval_real_item<KS, K, T>(A, item, pw + threadIdx.x, st + threadIdx.x);
         __syncthreads();
     }
 }
