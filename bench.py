@@ -96,7 +96,7 @@ def paper_workloads(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, m=16):
 # FETCH_SIZE and WRITE_SIZE passes calibrated with a 256 MiB copy (recorded
 # in profiles/qmc_eval_real_doublebox_n1000003_counters.md).  A class absent
 # here was not measured with the current kernel and reports null.
-TRAFFIC_BYTES = {(4, 0, 1000003, 16): 220.18e9, (3, 0, 1000003, 16): 8.080e9}
+TRAFFIC_BYTES = {(4, 0, 1000003, 16): 4.5245e9, (3, 0, 1000003, 16): 3.182e7}
 
 
 def parse():
