@@ -98,19 +98,21 @@ typedef struct {
  * orders above `top` are dropped by every operation. */
 typedef struct { cplx c[ORD_N]; } series;
 
-static int g_top;   /* highest order kept (set per call) */
-static int g_bot;   /* lowest order that can be non-zero (set per call) */
+/* Orders kept by the series operations of one call: top is the highest
+ * order kept, bot the lowest that can be non-zero.  Passed explicitly, so
+ * concurrent calls from different host threads do not interfere. */
+typedef struct { int top, bot; } lims;
 
 static void s_zero(series *s) { memset(s, 0, sizeof *s); }
 
 static void s_const(series *s, cplx v) { s_zero(s); s->c[-ORD_LO] = v; }
 
-/* product, truncated above g_top; every factor is zero below g_bot */
-static void s_mul(series *out, const series *x, const series *y)
+/* product, truncated above L->top; every factor is zero below L->bot */
+static void s_mul(const lims *L, series *out, const series *x, const series *y)
 {
     series r;
     s_zero(&r);
-    const int lo = g_bot - ORD_LO, hi = g_top - ORD_LO;
+    const int lo = L->bot - ORD_LO, hi = L->top - ORD_LO;
     for (int p = lo; p <= hi; ++p) {
         if (x->c[p] == 0) continue;
         for (int q = lo; q <= hi; ++q) {
@@ -122,17 +124,17 @@ static void s_mul(series *out, const series *x, const series *y)
     *out = r;
 }
 
-static void s_axpy(series *acc, cplx alpha, const series *x)
+static void s_axpy(const lims *L, series *acc, cplx alpha, const series *x)
 {
-    for (int p = g_bot - ORD_LO; p <= g_top - ORD_LO; ++p) acc->c[p] += alpha * x->c[p];
+    for (int p = L->bot - ORD_LO; p <= L->top - ORD_LO; ++p) acc->c[p] += alpha * x->c[p];
 }
 
 /* exp(v eps) as a series */
-static void s_exp_eps(series *s, cplx v)
+static void s_exp_eps(const lims *L, series *s, cplx v)
 {
     s_zero(s);
     cplx term = 1;
-    for (int k = 0; k <= g_top && -ORD_LO + k < ORD_N; ++k) {
+    for (int k = 0; k <= L->top && -ORD_LO + k < ORD_N; ++k) {
         s->c[-ORD_LO + k] = term;
         term = term * v / (real)(k + 1);
     }
@@ -146,10 +148,10 @@ static cplx logF(cplx x)
     return CLOG(x);
 }
 
-static void s_pow(series *s, cplx x, double p, double q)
+static void s_pow(const lims *lim, series *s, cplx x, double p, double q)
 {
     cplx L = logF(x);
-    s_exp_eps(s, (real)q * L);
+    s_exp_eps(lim, s, (real)q * L);
     cplx base = CEXP((real)p * L);
     for (int k = 0; k < ORD_N; ++k) s->c[k] *= base;
 }
@@ -279,7 +281,7 @@ static cplx cdet(int d, cplx *A)     /* Gaussian elimination, partial pivot */
 }
 
 /* h evaluated at the real point tp (integrand without prod_{J} t^(-1+b eps)) */
-static void h_series(const oracle_sector *s, const real *tp,
+static void h_series(const lims *L, const oracle_sector *s, const real *tp,
                      const real *omt, const int *inJ, double lambda,
                      series *h, int *bad_f, int *bad_u)
 {
@@ -315,22 +317,22 @@ static void h_series(const oracle_sector *s, const real *tp,
     for (int j = 0; j < d; ++j) {
         if (inJ[j]) {
             if (lambda > 0.0) {
-                s_pow(&f, phi[j], -1.0, s->b[j]);
-                s_mul(h, h, &f);
+                s_pow(L, &f, phi[j], -1.0, s->b[j]);
+                s_mul(L, h, h, &f);
             }
         } else {
-            s_pow(&f, z[j], s->a[j], s->b[j]);
-            s_mul(h, h, &f);
+            s_pow(L, &f, z[j], s->a[j], s->b[j]);
+            s_mul(L, h, h, &f);
         }
     }
-    s_pow(&f, Uz, s->u0, s->u1);
-    s_mul(h, h, &f);
-    s_pow(&f, Fz, s->f0, s->f1);
-    s_mul(h, h, &f);
+    s_pow(L, &f, Uz, s->u0, s->u1);
+    s_mul(L, h, h, &f);
+    s_pow(L, &f, Fz, s->f0, s->f1);
+    s_mul(L, h, h, &f);
 }
 
 /* g(t) with the subtraction of Eq. 11 for every j in J */
-static void integrand(const oracle_sector *s, const real *t,
+static void integrand(const lims *L, const oracle_sector *s, const real *t,
                       const real *omt, double lambda, series *g, int *bad_f,
                       int *bad_u)
 {
@@ -347,7 +349,7 @@ static void integrand(const oracle_sector *s, const real *t,
         memcpy(op, omt, sizeof(real) * d);
         for (int q = 0; q < nJ; ++q)
             if (X >> q & 1) { tp[J[q]] = 0.0; op[J[q]] = 1.0; }
-        h_series(s, tp, op, inJ, lambda, &hc[X], bad_f, bad_u);
+        h_series(L, s, tp, op, inJ, lambda, &hc[X], bad_f, bad_u);
     }
     s_zero(g);
     int full = ncorner - 1;
@@ -358,7 +360,7 @@ static void integrand(const oracle_sector *s, const real *t,
         s_zero(&inner);
         for (int S = rest;; S = (S - 1) & rest) {
             int parity = __builtin_popcount(S) & 1;
-            s_axpy(&inner, parity ? -1 : 1, &hc[R | S]);
+            s_axpy(L, &inner, parity ? -1 : 1, &hc[R | S]);
             if (S == 0) break;
         }
         series term = inner, f;
@@ -367,12 +369,12 @@ static void integrand(const oracle_sector *s, const real *t,
             if (R >> q & 1) {
                 s_div_eps(&term, &term, s->b[j]);
             } else {
-                s_exp_eps(&f, (real)s->b[j] * RLOG(t[j]));
+                s_exp_eps(L, &f, (real)s->b[j] * RLOG(t[j]));
                 for (int k = 0; k < ORD_N; ++k) f.c[k] /= t[j];
-                s_mul(&term, &term, &f);
+                s_mul(L, &term, &term, &f);
             }
         }
-        s_axpy(g, 1, &term);
+        s_axpy(L, g, 1, &term);
     }
     free(hc);
 }
@@ -416,8 +418,7 @@ int oracle_sector_sums(const oracle_sector *s, uint64_t n, const uint32_t *z,
     }
     int top = out_lo + out_len - 1;
     if (top + nJ >= ORD_LO + ORD_N) return -1;
-    g_top = top + nJ;       /* orders needed before the 1/eps divisions */
-    g_bot = -nJ;
+    const lims L = {top + nJ, -nJ};    /* orders needed before the 1/eps divisions */
 
     uint64_t nchunks = (n + CHUNK - 1) / CHUNK;
     size_t slots = (size_t)m * nchunks * out_len * 2;
@@ -454,7 +455,7 @@ int oracle_sector_sums(const oracle_sector *s, uint64_t n, const uint32_t *z,
             if (w == 0.0 || skip) { ++N[2]; continue; }
             series g;
             int bf = 0, bu = 0;
-            integrand(s, t, omt, lambda, &g, &bf, &bu);
+            integrand(&L, s, t, omt, lambda, &g, &bf, &bu);
             N[0] += bf != 0;
             N[1] += bu != 0;
             for (int q = 0; q < out_len; ++q) {
@@ -504,11 +505,10 @@ int oracle_point(const oracle_sector *s, const double *t, double lambda,
     for (int j = 0; j < s->dim; ++j) nJ += (s->a[j] == -1.0);
     int top = out_lo + out_len - 1;
     if (s->dim > MAXD || out_lo < ORD_LO || top + nJ >= ORD_LO + ORD_N) return -1;
-    g_top = top + nJ;
-    g_bot = -nJ;
+    const lims L = {top + nJ, -nJ};
     series g;
     int bf = 0, bu = 0;
-    integrand(s, tt, omt, lambda, &g, &bf, &bu);
+    integrand(&L, s, tt, omt, lambda, &g, &bf, &bu);
     for (int q = 0; q < out_len; ++q) {
         out[2 * q] = (double)CREAL(g.c[out_lo + q - ORD_LO]);
         out[2 * q + 1] = (double)CIMAG(g.c[out_lo + q - ORD_LO]);
