@@ -80,3 +80,43 @@ def compare_sectors(name, kin, n, m, eps_hi=0, lam=0.0, r=2, ppl=0, tol=1e-12,
     plan.close()
     assert worst <= tol, f"{name}: worst relative difference {worst:.3e} > {tol:.0e}"
     return res, worst
+
+
+def oracle_assembled(name, kin, n, z, shifts, eps_hi=0, lam=0.0, r=2, strategy="iterated",
+                     quad_from=2):
+    """The oracle's whole-problem result (Eqs. 19-20) on the given lattice and
+    shifts, with sectors of at least `quad_from` poles summed in binary128,
+    and a rounding scale per order: the largest over shifts of the same
+    assembly taken over |prefactor|, |D| and sum_i |w g|."""
+    osecs, oinfo = oracle_sectors(name, strategy)
+    nums = [oq.NumericSector(s, oinfo, kin) for s in osecs]
+    kmax = max(ns.nJ for ns in nums)
+    pref, pref_lo = oq.gamma_prefactor(oinfo, -2, eps_hi + kmax + 2)
+    sec_lo = -kmax
+    K = eps_hi - pref_lo - sec_lo + 1
+    per, per_abs = [], []
+    for ns in nums:
+        sums, abss, _ = oq.sector_sums(ns, n, z, shifts, r, oq.effective_lambda(ns, lam),
+                                       sec_lo, K, quad=ns.nJ >= quad_from)
+        per.append(sums)
+        per_abs.append((abss[..., 0] + abss[..., 1]).astype(complex))
+    D = [float(s.get("D", 1)) for s in osecs]
+    eps_lo = sec_lo + pref_lo
+    res = oq.assemble(per, D, pref, pref_lo, sec_lo, n, eps_lo, eps_hi)
+    absres = oq.assemble(per_abs, [abs(d) for d in D], {k: abs(v) for k, v in pref.items()},
+                         pref_lo, sec_lo, n, eps_lo, eps_hi)
+    res["scale"] = np.max(np.abs(absres["per_shift"]), axis=0)
+    return res
+
+
+def assert_assembly_matches(gpu, ora, point=0, tol=1e-12):
+    """Mean and Eq. 20 errors of one kinematic point of a GPU result equal the
+    oracle's within tol times the oracle's rounding scale per order."""
+    assert list(gpu["orders"]) == list(ora["orders"])
+    sc = ora["scale"]
+    assert np.all(np.abs(gpu["mean"][point] - ora["mean"]) <= tol * sc), \
+        (gpu["mean"][point], ora["mean"], sc)
+    assert np.all(np.abs(gpu["err_re"][point] - ora["err_re"]) <= 2 * tol * sc), \
+        (gpu["err_re"][point], ora["err_re"])
+    assert np.all(np.abs(gpu["err_im"][point] - ora["err_im"]) <= 2 * tol * sc), \
+        (gpu["err_im"][point], ora["err_im"])

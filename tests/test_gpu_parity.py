@@ -7,7 +7,8 @@ the FP64 parity bar.  Sizes span several work tiles and a ragged tail.
 import numpy as np
 import pytest
 
-from gpu_util import compare_sectors, ctx, gpu_plan, sample_sectors
+from gpu_util import (assert_assembly_matches, compare_sectors, ctx, gpu_plan,
+                      oracle_assembled, sample_sectors)
 from oracle import qmc as oq
 from oracle.decompose import decompose as odec
 from paper_1508_02512_amd import frontend as fe
@@ -72,19 +73,21 @@ def test_double_box_offshell_table1_columns(legs):
                     sectors=sample_sectors(f"doublebox_off{legs}", per_class=4))
 
 
-def test_tiny_lattice_and_result_assembly():
-    """n = 2 (a single partial tile) and the assembled Laurent series equal the
-    oracle's assembly of the same sums."""
-    print("box n=2 / assembly", flush=True)
-    compare_sectors("box", {"s": -3.0, "t": -2.0}, 1009, 2)
+@pytest.mark.parametrize("n,m", [(2, 3), (1009, 2), (10007, 7)])
+def test_tiny_lattice_and_result_assembly(n, m):
+    """n = 2 (a single partial tile) and larger lattices: the assembled
+    Laurent series (Eq. 19) and its errors (Eq. 20) equal the oracle's
+    assembly of its own sums, order by order, within 1e-12 of the rounding
+    scale."""
+    print(f"box n={n} m={m} / assembly", flush=True)
+    kin = {"s": -3.0, "t": -2.0}
     plan, info = gpu_plan("box")
     z = lattice(1009)
-    sh = shift_table(3, 3, 8)
-    res = plan.integrate(fe.kin_vector(info, {"s": -3.0, "t": -2.0}), (2, z), sh,
-                         sector_sums=True)
+    sh = shift_table(3, m, 8)
+    res = plan.integrate(fe.kin_vector(info, kin), (n, z), sh)
     assert np.all(np.isfinite(res["mean"]))
-    ores = oq.integrate(PROBLEMS["box"], {"s": -3.0, "t": -2.0}, 2, z, sh)
-    assert np.allclose(res["mean"][0], ores["mean"], rtol=1e-12, atol=1e-14)
+    assert_assembly_matches(res, oracle_assembled("box", kin, n, z, sh))
+    assert np.all(res["err_re"][0] > 0)
     plan.close()
 
 
@@ -174,11 +177,16 @@ def test_double_box_benchmark_config_sampled():
     poles = [sum(1 for a in s["a"] if a == -1) for s in osecs]
     pick = [i for i, p in enumerate(poles) if p == 0][::3] + \
         [i for i, p in enumerate(poles) if p == 1][::40][:4]
+    # one sector of the dominant class (four poles, the launch with the
+    # compensated sums in LDS), against the binary128 oracle
+    four = [i for i, p in enumerate(poles) if p == 4]
+    pick.append(four[len(four) // 2])
     z = lattice(n)
     for s in pick:
         ns = oq.NumericSector(osecs[s], oinfo, kin_vals)
+        print(f"  oracle sector {s} ({ns.nJ} poles) at n={n}", flush=True)
         sums, abss, _ = oq.sector_sums(ns, n, z, sh[:1], 2, 0.0, res["sec_lo"],
-                                       plan.info.sec_orders)
+                                       plan.info.sec_orders, nthreads=16, quad=ns.nJ >= 2)
         gpu = res["sector_sums"][0, s, :1]
         scale = abss[..., 0] + abss[..., 1]
         assert np.all(np.abs(gpu - sums) <= 1e-12 * scale), s

@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from gpu_util import ctx, gpu_plan
+from gpu_util import assert_assembly_matches, ctx, gpu_plan, oracle_assembled
 from paper_1508_02512_amd import frontend as fe
 from paper_1508_02512_amd import qmc
 from seeded_inputs.lattice import lattice
@@ -33,6 +33,27 @@ def test_single_request_converges_and_matches_integrate():
     assert np.allclose(r["err_re"], ref["err_re"], rtol=1e-8, atol=1e-16)
     want = np.array([0.666666666666667, -0.982063599677040, -1.48360889993076])
     assert np.all(np.abs(r["mean"][0].real - want) <= 6 * r["err_re"][0] + 1e-12)
+    plan.close()
+
+
+@pytest.mark.parametrize("name,kin,lam,m", [
+    ("box", {"s": -3.0, "t": -2.0}, 0.0, 8),
+    ("np_vertex", {"s": 4.5, "msq": 1.0}, 0.5, 4),
+])
+def test_served_doubling_matches_oracle(name, kin, lam, m):
+    """A request that doubles n = 2^10 -> 2^11 -> 2^12 (the last two steps
+    over the odd indices of the embedded lattice only) and then stops at
+    n_max: its mean and Eq. 20 errors equal the oracle's on all 2^12 points
+    of the same lattice and shifts, within 1e-12 of the rounding scale.
+    The non-planar vertex takes the deformed kernel."""
+    print(f"serve vs oracle: {name}", flush=True)
+    plan, info = gpu_plan(name, lam=lam)
+    seed = 21
+    r = qmc.submit(plan, fe.kin_vector(info, kin), 1e-15, 1 << 10, 1 << 12, m, seed,
+                   Z).wait(120)
+    assert r["rc"] == -7 and r["n_final"] == 1 << 12 and r["steps"] == 3
+    ora = oracle_assembled(name, kin, 1 << 12, Z, shift_table(seed, m, 8), lam=lam)
+    assert_assembly_matches(r, ora)
     plan.close()
 
 
