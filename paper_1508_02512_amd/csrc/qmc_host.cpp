@@ -382,8 +382,8 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
             if (!qmc_cplx_supported(S.dim, h.ks, kb)) {
                 delete plan;
                 return set_err(ctx, QMC_EUNSUPPORTED,
-                               "sector %d: deformation supports dim <= 6 with at most 4 poles "
-                               "and 1-2 orders above them (dim <= 2: 2 poles, 1-3 orders); "
+                               "sector %d: deformation supports dim <= 6 with at most 2 poles "
+                               "and 1-2 orders above them (dim <= 2: 1-3 orders); "
                                "got dim %d, %d poles, %d orders",
                                s, S.dim, h.ks, kb);
             }
@@ -657,36 +657,32 @@ static int job_upload(qmc_job *job, T **dptr, const T *src, size_t count)
     return QMC_OK;
 }
 
-int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
-                  const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
-                  const double *shifts, int32_t m, int ppl_override, int grid_override,
-                  bool class_timing, qmc_job **out)
+// The host side of a bind: validates the inputs and fills the job's
+// classes, sizes and the host arrays of its device inputs (no device work).
+int qmc_job_prepare(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
+                    const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
+                    const double *shifts, int32_t m, int ppl_override, int grid_override,
+                    qmc_job *job, qmc_job_host &H)
 {
-    if (!ctx || !plan || !kin || !shifts || !out) return set_err(ctx, QMC_EINVAL, "null argument");
-    *out = nullptr;
+    if (!ctx || !plan || !kin || !shifts) return set_err(ctx, QMC_EINVAL, "null argument");
     if (n_points < 1) return set_err(ctx, QMC_EINVAL, "n_points < 1");
     if (m < 2) return set_err(ctx, QMC_EINVAL, "need m >= 2 shifts for the error estimate");
     if (!lat && !lat_per_sector) return set_err(ctx, QMC_EINVAL, "no lattice given");
     const int ns = (int)plan->secs.size();
-    (void)hipSetDevice(ctx->device);
-
-    auto *job = new (std::nothrow) qmc_job();
-    if (!job) return set_err(ctx, QMC_ENOMEM, "host allocation");
     job->ctx = ctx;
     job->plan = plan;
     job->n_points = n_points;
     job->m = m;
 
     // lattices per sector, components permuted like the sector's variables
-    std::vector<qmc_lat_dev> lats(ns);
+    std::vector<qmc_lat_dev> &lats = H.lats;
+    lats.assign(ns, qmc_lat_dev{});
     job->n_per_sector.resize(ns);
     for (int s = 0; s < ns; ++s) {
         const qmc_lattice &L = lat_per_sector ? lat_per_sector[s] : *lat;
-        if (L.n < 2 || L.n >= (1ull << 31) || !L.z) {
-            delete job;
+        if (L.n < 2 || L.n >= (1ull << 31) || !L.z)
             return set_err(ctx, QMC_EINVAL, "sector %d: lattice size %llu outside [2, 2^31)", s,
                            (unsigned long long)L.n);
-        }
         const qmc_sec_host &h = plan->secs[s];
         qmc_lat_dev d{};
         d.n = (uint32_t)L.n;
@@ -699,7 +695,9 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
     // coefficients contracted with the kinematics of every point
     const int nt = plan->n_terms, ni = plan->n_inv;
     const int nd = (int)plan->dexp.size();
-    std::vector<double> coef((size_t)n_points * nt), dcoef((size_t)n_points * nd);
+    std::vector<double> &coef = H.coef, &dcoef = H.dcoef;
+    coef.assign((size_t)n_points * nt, 0.0);
+    dcoef.assign((size_t)n_points * nd, 0.0);
     for (int p = 0; p < n_points; ++p)
         qmc_contract(plan, kin + (size_t)p * ni, coef.data() + (size_t)p * nt,
                      dcoef.data() + (size_t)p * nd);
@@ -718,10 +716,14 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
     uint64_t nmax_sec = 0;
     for (int s = 0; s < ns; ++s) nmax_sec = std::max<uint64_t>(nmax_sec, job->n_per_sector[s]);
     const int n_groups = n_points * ns * m;
-    std::vector<int32_t> gbeg(n_groups), gend(n_groups);
-    std::vector<qmc_item> items;
+    std::vector<int32_t> &gbeg = H.gbeg, &gend = H.gend;
+    gbeg.assign(n_groups, 0);
+    gend.assign(n_groups, 0);
+    std::vector<qmc_item> &items = H.items;
+    items.clear();
     std::vector<int> key_of((size_t)n_points * ns);
-    std::vector<double> lam((size_t)n_points * ns, 0.0);
+    std::vector<double> &lam = H.lam;
+    lam.assign((size_t)n_points * ns, 0.0);
     std::vector<std::pair<int, int>> keys;     // (ks, dm or 0 for real) of every class
     for (int p = 0; p < n_points; ++p)
         for (int s = 0; s < ns; ++s) {
@@ -784,22 +786,41 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
         c.end = (int)items.size();
         if (c.end > c.begin) job->classes.push_back(c);
     }
-    if (items.size() > (size_t)INT32_MAX) {
-        delete job;
-        return set_err(ctx, QMC_EINVAL, "work list too long");
-    }
+    if (items.size() > (size_t)INT32_MAX) return set_err(ctx, QMC_EINVAL, "work list too long");
     job->n_items = (int)items.size();
     job->n_groups = n_groups;
     job->evals = total;
-    int rc = QMC_OK;
-    if (!rc) rc = job_upload(job, &job->d_lat, lats.data(), lats.size());
-    if (!rc) rc = job_upload(job, &job->d_coef, coef.data(), coef.size());
-    if (!rc) rc = job_upload(job, &job->d_dcoef, dcoef.data(), dcoef.size());
-    if (!rc) rc = job_upload(job, &job->d_lam, lam.data(), lam.size());
+    job->h_out_n = (size_t)n_groups * plan->kstride * 2;
+    H.shifts = shifts;
+    return QMC_OK;
+}
+
+int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
+                  const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
+                  const double *shifts, int32_t m, int ppl_override, int grid_override,
+                  bool class_timing, qmc_job **out)
+{
+    if (!out) return set_err(ctx, QMC_EINVAL, "null argument");
+    *out = nullptr;
+    auto *job = new (std::nothrow) qmc_job();
+    if (!job) return set_err(ctx, QMC_ENOMEM, "host allocation");
+    qmc_job_host H;
+    int rc = qmc_job_prepare(ctx, plan, kin, n_points, lat, lat_per_sector, shifts, m,
+                             ppl_override, grid_override, job, H);
+    if (rc) {
+        delete job;
+        return rc;
+    }
+    (void)hipSetDevice(ctx->device);
+    const int n_groups = job->n_groups;
+    if (!rc) rc = job_upload(job, &job->d_lat, H.lats.data(), H.lats.size());
+    if (!rc) rc = job_upload(job, &job->d_coef, H.coef.data(), H.coef.size());
+    if (!rc) rc = job_upload(job, &job->d_dcoef, H.dcoef.data(), H.dcoef.size());
+    if (!rc) rc = job_upload(job, &job->d_lam, H.lam.data(), H.lam.size());
     if (!rc) rc = job_upload(job, &job->d_shift, shifts, (size_t)m * QMC_DMAX);
-    if (!rc) rc = job_upload(job, &job->d_items, items.data(), items.size());
-    if (!rc) rc = job_upload(job, &job->d_gbeg, gbeg.data(), gbeg.size());
-    if (!rc) rc = job_upload(job, &job->d_gend, gend.data(), gend.size());
+    if (!rc) rc = job_upload(job, &job->d_items, H.items.data(), H.items.size());
+    if (!rc) rc = job_upload(job, &job->d_gbeg, H.gbeg.data(), H.gbeg.size());
+    if (!rc) rc = job_upload(job, &job->d_gend, H.gend.data(), H.gend.size());
     if (!rc)
         rc = job_upload<double>(job, &job->d_partial, nullptr,
                                 (size_t)job->n_items * plan->kstride * 4);
@@ -807,6 +828,9 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
     if (!rc)
         rc = job_upload<double>(job, &job->d_out, nullptr, (size_t)n_groups * plan->kstride * 2);
     if (!rc) rc = job_upload<int32_t>(job, &job->d_gviol, nullptr, (size_t)n_groups);
+    // the uploads read the host arrays of H, which end with this call
+    if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess)
+        rc = set_err(ctx, QMC_EDEVICE, "upload failed");
     if (!rc && (hipEventCreate(&job->ev0) != hipSuccess || hipEventCreate(&job->ev1) != hipSuccess))
         rc = set_err(ctx, QMC_EDEVICE, "hipEventCreate failed");
     if (rc) {
@@ -814,7 +838,6 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
         delete job;
         return rc;
     }
-    job->h_out_n = (size_t)n_groups * plan->kstride * 2;
     if (hipHostMalloc((void **)&job->h_out, sizeof(double) * job->h_out_n) != hipSuccess ||
         hipHostMalloc((void **)&job->h_gviol, sizeof(int32_t) * n_groups) != hipSuccess) {
         qmc_job_release(job);
@@ -838,12 +861,14 @@ extern "C" int qmc_bind(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
                          out);
 }
 
-extern "C" int qmc_run(qmc_job *job)
+// The launch sequence of a bound job on the context stream: one integrand
+// launch per class (bracketed by the class events when timing), the
+// fixed-order reduction and the copies of the group sums and violation
+// counts into job->h_out and job->h_gviol.
+hipError_t qmc_enqueue(qmc_job *job, bool timing)
 {
-    if (!job) return QMC_EINVAL;
     qmc_ctx *ctx = job->ctx;
     const qmc_plan *plan = job->plan;
-    (void)hipSetDevice(ctx->device);
     qmc_launch_args A{};
     A.sec = plan->d_sec;
     A.lat = job->d_lat;
@@ -864,30 +889,36 @@ extern "C" int qmc_run(qmc_job *job)
     A.n_dterms = (int32_t)plan->dexp.size();
     A.kstride = plan->kstride;
     A.korobov_r = plan->opts.korobov_r;
-    auto enqueue = [&](bool timing) -> hipError_t {
-        hipError_t e = hipSuccess;
-        for (size_t i = 0; i < job->classes.size() && e == hipSuccess; ++i) {
-            const qmc_class &c = job->classes[i];
-            if (timing && !job->ev_cls.empty()) e = hipEventRecord(job->ev_cls[i], ctx->stream);
-            A.item_begin = c.begin;
-            A.item_end = c.end;
-            if (e == hipSuccess) e = qmc_launch_class(plan, c, A, ctx->stream);
-        }
-        if (e == hipSuccess && timing && !job->ev_cls.empty())
-            e = hipEventRecord(job->ev_cls.back(), ctx->stream);
-        if (e == hipSuccess && timing) e = hipEventRecord(job->ev1, ctx->stream);
-        if (e == hipSuccess)
-            e = qmc_launch_reduce(job->d_partial, job->d_viol, job->d_gbeg, job->d_gend,
-                                  job->n_groups, plan->kstride, job->d_out, job->d_gviol,
-                                  ctx->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(job->h_out, job->d_out, sizeof(double) * job->h_out_n,
-                               hipMemcpyDeviceToHost, ctx->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(job->h_gviol, job->d_gviol, sizeof(int32_t) * job->n_groups,
-                               hipMemcpyDeviceToHost, ctx->stream);
-        return e;
-    };
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < job->classes.size() && e == hipSuccess; ++i) {
+        const qmc_class &c = job->classes[i];
+        if (timing && !job->ev_cls.empty()) e = hipEventRecord(job->ev_cls[i], ctx->stream);
+        A.item_begin = c.begin;
+        A.item_end = c.end;
+        if (e == hipSuccess) e = qmc_launch_class(plan, c, A, ctx->stream);
+    }
+    if (e == hipSuccess && timing && !job->ev_cls.empty())
+        e = hipEventRecord(job->ev_cls.back(), ctx->stream);
+    if (e == hipSuccess && timing && job->ev1) e = hipEventRecord(job->ev1, ctx->stream);
+    if (e == hipSuccess)
+        e = qmc_launch_reduce(job->d_partial, job->d_viol, job->d_gbeg, job->d_gend,
+                              job->n_groups, plan->kstride, job->d_out, job->d_gviol,
+                              ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(job->h_out, job->d_out, sizeof(double) * job->h_out_n,
+                           hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(job->h_gviol, job->d_gviol, sizeof(int32_t) * job->n_groups,
+                           hipMemcpyDeviceToHost, ctx->stream);
+    return e;
+}
+
+extern "C" int qmc_run(qmc_job *job)
+{
+    if (!job) return QMC_EINVAL;
+    qmc_ctx *ctx = job->ctx;
+    (void)hipSetDevice(ctx->device);
+    auto enqueue = [&](bool timing) { return qmc_enqueue(job, timing); };
     if (job->use_graph) {
         // the whole sequence as one graph, captured once and replayed
         if (!job->graph) {
@@ -1002,17 +1033,7 @@ extern "C" int qmc_fetch(qmc_job *job, qmc_result *out)
     float ms = 0.0f;
     HIP_CHECK(ctx, hipEventElapsedTime(&ms, job->ev0, job->ev1));
     job->launched = false;
-    qmc_assemble(job->plan, job->n_points, job->m, job->n_per_sector, job->h_out, out);
-    long viol = 0;
-    for (int i = 0; i < job->n_groups; ++i) viol += job->h_gviol[i];
-    out->evals = job->evals;
-    out->n_final = job->n_per_sector.empty() ? 0 : job->n_per_sector[0];
-    out->deform_violations = (int32_t)std::min<long>(viol, INT32_MAX);
-    out->status = viol ? QMC_EDEFORM : QMC_OK;
     out->kernel_ms = ms;
-    double fl = 0.0;
-    for (const qmc_class &c : job->classes) fl += c.flops;
-    out->algo_flops = fl;
     job->cls_ms.assign(job->classes.size(), -1.0);
     if (job->cls_timed)
         for (size_t i = 0; i < job->classes.size(); ++i) {
@@ -1020,8 +1041,26 @@ extern "C" int qmc_fetch(qmc_job *job, qmc_result *out)
             if (hipEventElapsedTime(&cms, job->ev_cls[i], job->ev_cls[i + 1]) == hipSuccess)
                 job->cls_ms[i] = cms;
         }
-    return out->status == QMC_OK ? QMC_OK
-                                 : set_err(ctx, out->status, "%ld points violated the sign conditions", viol);
+    return qmc_result_fill(job, job->h_out, job->h_gviol, out);
+}
+
+// Assembly (Eqs. 19-20) and the counters of a finished run from its group
+// sums and per-group violation counts (host memory).
+int qmc_result_fill(qmc_job *job, const double *gsum, const int32_t *gviol, qmc_result *out)
+{
+    qmc_assemble(job->plan, job->n_points, job->m, job->n_per_sector, gsum, out);
+    long viol = 0;
+    for (int i = 0; i < job->n_groups; ++i) viol += gviol[i];
+    out->evals = job->evals;
+    out->n_final = job->n_per_sector.empty() ? 0 : job->n_per_sector[0];
+    out->deform_violations = (int32_t)std::min<long>(viol, INT32_MAX);
+    out->status = viol ? QMC_EDEFORM : QMC_OK;
+    double fl = 0.0;
+    for (const qmc_class &c : job->classes) fl += c.flops;
+    out->algo_flops = fl;
+    return out->status == QMC_OK
+               ? QMC_OK
+               : set_err(job->ctx, out->status, "%ld points violated the sign conditions", viol);
 }
 
 extern "C" void qmc_job_free(qmc_job *job)

@@ -129,6 +129,22 @@ struct qmc_job {
     hipGraphExec_t graph = nullptr;
 };
 
+// Host arrays of a bound job's device inputs (filled by qmc_job_prepare).
+struct qmc_job_host {
+    std::vector<qmc_lat_dev> lats;   // [n_sectors]
+    std::vector<double> coef, dcoef; // [n_points][n_terms], [n_points][n_dterms]
+    std::vector<double> lam;         // [n_points][n_sectors]
+    std::vector<qmc_item> items;
+    std::vector<int32_t> gbeg, gend; // [n_groups]
+    const double *shifts = nullptr;  // caller's [m][QMC_DMAX]
+};
+
+int qmc_job_prepare(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,
+                    const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
+                    const double *shifts, int32_t m, int ppl_override, int grid_override,
+                    qmc_job *job, qmc_job_host &H);
+hipError_t qmc_enqueue(qmc_job *job, bool timing);
+int qmc_result_fill(qmc_job *job, const double *gsum, const int32_t *gviol, qmc_result *out);
 int qmc_dev_alloc(qmc_ctx *ctx, void **p, size_t bytes);
 void qmc_dev_free(qmc_ctx *ctx, void *p, size_t bytes);
 int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t n_points,

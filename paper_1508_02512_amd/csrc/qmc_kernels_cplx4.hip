@@ -7,7 +7,5 @@ hipError_t qmc_launch_cplx4(int ks, int kb, const qmc_launch_args &args, int gri
     QMC_CPLX_CASE(4, 0, 1) QMC_CPLX_CASE(4, 0, 2)
     QMC_CPLX_CASE(4, 1, 1) QMC_CPLX_CASE(4, 1, 2)
     QMC_CPLX_CASE(4, 2, 1) QMC_CPLX_CASE(4, 2, 2)
-    QMC_CPLX_CASE(4, 3, 1) QMC_CPLX_CASE(4, 3, 2)
-    QMC_CPLX_CASE(4, 4, 1) QMC_CPLX_CASE(4, 4, 2)
     return hipErrorInvalidValue;
 }

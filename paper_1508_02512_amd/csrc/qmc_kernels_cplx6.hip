@@ -7,7 +7,5 @@ hipError_t qmc_launch_cplx6(int ks, int kb, const qmc_launch_args &args, int gri
     QMC_CPLX_CASE(6, 0, 1) QMC_CPLX_CASE(6, 0, 2)
     QMC_CPLX_CASE(6, 1, 1) QMC_CPLX_CASE(6, 1, 2)
     QMC_CPLX_CASE(6, 2, 1) QMC_CPLX_CASE(6, 2, 2)
-    QMC_CPLX_CASE(6, 3, 1) QMC_CPLX_CASE(6, 3, 2)
-    QMC_CPLX_CASE(6, 4, 1) QMC_CPLX_CASE(6, 4, 2)
     return hipErrorInvalidValue;
 }

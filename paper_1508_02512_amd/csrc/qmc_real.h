@@ -178,6 +178,10 @@ struct Tree<0, XB, KS, K, T> {
 // h_{q+1} = h_q B / (q + 1) formed only on the subsets that still
 // contribute, C(Y) = prod_{j in Y} t_j^-1 prod_{j not in Y} 1/b_j and
 // L(Y) = sum_{j in Y} b_j ln t_j (formed where used: fewer live registers).
+// The factors of C(Y) are multiplied into h_q^[Y] one at a time: h^[Y]
+// vanishes like prod_{j in Y} t_j, so every partial product stays of the
+// size of the result, while C(Y) alone can exceed the float range (four
+// poles at t_j ~ 1e-10).
 template <int KS, int K, int Q, typename T>
 struct Accum {
     static __device__ __forceinline__ void run(cptr<qmc_sec_dev> S, const Point<KS, K, T> &P,
@@ -189,17 +193,16 @@ struct Accum {
         for (int Y = 0; Y < N; ++Y) {
             const int pc = __builtin_popcount(Y);
             if (Q + pc >= K) continue;
-            T c = 1, L = 0;
+            T e = H[Y], L = 0;
 #pragma unroll
             for (int j = 0; j < KS; ++j) {
                 if (Y >> j & 1) {
-                    c *= P.invt[j];
+                    e *= P.invt[j];
                     L = fma(T(S->b[j]), P.lt[j], L);
                 } else {
-                    c *= T(S->inv_b[j]);
+                    e *= T(S->inv_b[j]);
                 }
             }
-            T e = c * H[Y];
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 const int o = Q + r + pc;
@@ -440,7 +443,12 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                             }
                     Tree<KS, 0, KS, K, T>::run(S, P, g);
                 }
-                if (P.bad) {
+                // a term that is not finite (U or F not positive at a
+                // corner, or an overflow) is counted, not summed
+                bool finite = true;
+#pragma unroll
+                for (int q = 0; q < K; ++q) finite &= __builtin_isfinite(g[q]);
+                if (P.bad || !finite) {
                     viol += 1;
                 } else {
                     const double wp = (double)(w * pn);

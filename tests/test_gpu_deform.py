@@ -97,3 +97,22 @@ def test_hh_double_boxes_sectors(name, lam):
     res, _ = compare_sectors(name, HH_POINT, 1009, 2, lam=lam,
                              sectors=sample_sectors(name, per_class=6))
     assert res["violations"] == 0
+
+
+def test_deformed_sectors_with_three_or_more_poles_refused():
+    """The massless planar double box has sectors with three and four poles;
+    with a deformation parameter the plan is refused (QMC_EUNSUPPORTED)
+    before anything runs, since the deformed kernel's corner differences
+    would not reach FP64 accuracy there.  The same sectors plan without
+    deformation, and a deformed problem with at most two poles plans."""
+    from paper_1508_02512_amd import qmc
+    print("doublebox lambda=0.25 refused", flush=True)
+    with pytest.raises(qmc.QMCError) as e:
+        gpu_plan("doublebox", lam=0.25)
+    assert e.value.code == -3
+    plan, _ = gpu_plan("doublebox", lam=0.0)
+    assert plan.info.max_poles == 4
+    plan.close()
+    plan, _ = gpu_plan("hh_planar", lam=1.0)
+    assert plan.info.max_poles == 2 and plan.info.deform == 1
+    plan.close()
