@@ -169,6 +169,30 @@ int qmc_integrate(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
                   const qmc_lattice *lat_per_sector, const double *shifts,
                   int32_t m, qmc_result *out);
 
+/* ---- allocation-free variant ------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * qmc_integrate_noalloc computes exactly what qmc_integrate computes (same
+ * kernels, work list and summation order, hence the same bits), but every
+ * device buffer of the call lives in one fixed device array of
+ * QMC_NOALLOC_SCRATCH_BYTES that the library reserves on each device it is
+ * loaded on and keeps until the process ends; the call makes no device or
+ * pinned-host allocation (host-side planning still uses the C++ heap).
+ * Sizes: the call needs about 200 bytes per work item (items are tiles of
+ * 256 x points-per-lane lattice indices of one point, sector and shift) plus
+ * the contracted coefficients; a call that needs more than the array
+ * returns QMC_EBUDGET with the size it needed and runs nothing.  Every call
+ * on a device shares that device's array: calls on one device are
+ * serialised by the library and each waits for its stream to drain before
+ * it returns, so overlapping calls from several host threads are safe but
+ * run one after another.  kernel_ms is reported as 0.  Errors as for
+ * qmc_integrate. */
+#define QMC_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int qmc_integrate_noalloc(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
+                          int32_t n_points, const qmc_lattice *lat,
+                          const qmc_lattice *lat_per_sector, const double *shifts,
+                          int32_t m, qmc_result *out);
+
 /* The same in three steps: bind uploads the inputs and allocates device
  * outputs; run enqueues the kernels on the context stream (asynchronous);
  * fetch waits for them, copies the per-shift sums back and assembles. */

@@ -105,6 +105,11 @@ extern "C" int qmc_create(int device, size_t hbm_budget, int max_slots, qmc_ctx 
         return QMC_EDEVICE;
     }
     ctx->stream = ctx->own_stream;
+    if (qmc_noalloc_setup(device) != QMC_OK) {
+        (void)hipStreamDestroy(ctx->own_stream);
+        delete ctx;
+        return QMC_EDEVICE;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->n_cu = prop.multiProcessorCount;

@@ -161,3 +161,6 @@ int qmc_sector_mode(const qmc_plan *plan, int s, const double *coef, double *lam
 hipError_t qmc_launch_class(const qmc_plan *plan, const qmc_class &c, const qmc_launch_args &A,
                             hipStream_t stream);
 int qmc_set_error(qmc_ctx *ctx, int code, const char *fmt, ...);
+// Looks up the device address of the allocation-free entry point's scratch
+// array on `device` (which must be current); called once per context.
+int qmc_noalloc_setup(int device);

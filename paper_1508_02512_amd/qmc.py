@@ -23,6 +23,7 @@ ERRORS = {-1: "QMC_EINVAL", -2: "QMC_EUNREGULATED", -3: "QMC_EUNSUPPORTED",
 QMC_FP64, QMC_FP32_EVAL = 0, 1
 QMC_MATH_LN, QMC_MATH_LN1P, QMC_MATH_EXP, QMC_MATH_EXPM1 = 0, 1, 2, 3
 QMC_MAX_DIM = 8
+QMC_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 P = C.POINTER
 
@@ -101,6 +102,9 @@ _SIGS = {
     "qmc_integrate": (C.c_int, [C.c_void_p, C.c_void_p, P(C.c_double), C.c_int32,
                                 P(qmc_lattice), P(qmc_lattice), P(C.c_double), C.c_int32,
                                 P(qmc_result)]),
+    "qmc_integrate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, P(C.c_double), C.c_int32,
+                                        P(qmc_lattice), P(qmc_lattice), P(C.c_double),
+                                        C.c_int32, P(qmc_result)]),
     "qmc_bind": (C.c_int, [C.c_void_p, C.c_void_p, P(C.c_double), C.c_int32,
                            P(qmc_lattice), P(qmc_lattice), P(C.c_double), C.c_int32,
                            P(C.c_void_p)]),
@@ -304,14 +308,16 @@ class Plan:
         return out
 
     def integrate(self, kin, lattice, shifts, lat_per_sector=None, sector_sums=False,
-                  per_shift=False, allow_violations=False):
-        """lattice = (n, z[8]); shifts [m][8]; kin [n_points][n_inv]."""
+                  per_shift=False, allow_violations=False, noalloc=False):
+        """lattice = (n, z[8]); shifts [m][8]; kin [n_points][n_inv].
+        noalloc=True calls qmc_integrate_noalloc instead of qmc_integrate."""
         kin, shifts, lat, lps = self._inputs(kin, lattice, shifts, lat_per_sector)
         res, coeff, ss, ps = self._result(kin.shape[0], shifts.shape[0], sector_sums,
                                           per_shift)
-        rc = lib().qmc_integrate(self.ctx.h, self.h, _dptr(kin), kin.shape[0],
-                                 C.byref(lat) if lat is not None else None, lps,
-                                 _dptr(shifts), shifts.shape[0], C.byref(res))
+        fn = lib().qmc_integrate_noalloc if noalloc else lib().qmc_integrate
+        rc = fn(self.ctx.h, self.h, _dptr(kin), kin.shape[0],
+                C.byref(lat) if lat is not None else None, lps,
+                _dptr(shifts), shifts.shape[0], C.byref(res))
         if rc < 0 and not (allow_violations and rc == -6):
             self.ctx.check(rc)
         return self._pack(res, coeff, ss, ps, kin.shape[0])

@@ -59,3 +59,11 @@ def test_binding_structs_match_header_layout(tmp_path):
         assert int(got[name]) == ctypes.sizeof(T), name
         for f, _ in T._fields_:
             assert int(got[f"{name}.{f}"]) == getattr(T, f).offset, f"{name}.{f}"
+
+
+def test_noalloc_scratch_size_matches_binding():
+    text = open(os.path.join(ROOT, "include", "qmc.h")).read()
+    m = re.search(r"#define QMC_NOALLOC_SCRATCH_BYTES \((\d+)u \* (\d+)u \* (\d+)u\)", text)
+    assert m, "QMC_NOALLOC_SCRATCH_BYTES not found"
+    size = int(m.group(1)) * int(m.group(2)) * int(m.group(3))
+    assert size == qmc.QMC_NOALLOC_SCRATCH_BYTES
