@@ -237,7 +237,9 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
 
     auto *plan = new (std::nothrow) qmc_plan();
     if (!plan) return set_err(ctx, QMC_ENOMEM, "host allocation");
+    static std::atomic<uint64_t> next_plan_id{1};
     plan->ctx = ctx;
+    plan->id = next_plan_id++;
     plan->opts = o;
     plan->n_inv = pb->n_inv;
     plan->eps_lo = pb->eps_lo;
@@ -533,6 +535,14 @@ extern "C" void qmc_plan_free(qmc_plan *plan)
 {
     if (!plan) return;
     qmc_ctx *ctx = plan->ctx;
+    {
+        // the autotuner's choices for this plan go with it
+        std::lock_guard<std::mutex> g(ctx->tune_mu);
+        const std::string prefix = std::to_string((unsigned long long)plan->id) + "/";
+        for (auto it = ctx->tuned.begin(); it != ctx->tuned.end();)
+            it = it->first.compare(0, prefix.size(), prefix) == 0 ? ctx->tuned.erase(it)
+                                                                  : std::next(it);
+    }
     qmc_dev_free(ctx, plan->d_sec, sizeof(qmc_sec_dev) * plan->secs.size());
     qmc_dev_free(ctx, plan->d_texp, sizeof(uint32_t) * plan->texp.size());
     qmc_dev_free(ctx, plan->d_texpd, sizeof(double) * plan->texp.size() * QMC_DMAX);
@@ -641,7 +651,9 @@ std::string qmc_tune_key(const qmc_plan *plan, int ks, int dm, uint64_t n)
     int lg = 0;
     while ((2ull << lg) <= n) ++lg;
     char buf[128];
-    snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d", (const void *)plan, ks, dm,
+    // keyed by the plan's id, never its address: a freed plan's address
+    // can be reused by a later, different plan
+    snprintf(buf, sizeof buf, "%llu/%d/%d/%d/%d", (unsigned long long)plan->id, ks, dm,
              plan->opts.precision, lg);
     return buf;
 }

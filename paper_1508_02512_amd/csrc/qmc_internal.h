@@ -64,6 +64,7 @@ struct qmc_sec_host {
 
 struct qmc_plan {
     qmc_ctx *ctx = nullptr;
+    uint64_t id = 0;                 // unique per process: keys the autotuner's choices
     qmc_plan_opts opts{};
     int n_inv = 0;
     int eps_lo = 0, eps_hi = 0, eps_pref_lo = 0, n_pref = 0;
