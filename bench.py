@@ -91,12 +91,38 @@ def paper_workloads(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, m=16):
     return out
 
 
-# HBM bytes (read + written) per launch of the integrand kernel for a
-# (poles, complex width, n, m) class of this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE passes calibrated with a 256 MiB copy (recorded
-# in profiles/qmc_eval_real_doublebox_n1000003_counters.md).  A class absent
-# here was not measured with the current kernel and reports null.
-TRAFFIC_BYTES = {(4, 0, 1000003, 16): 4.5245e9, (3, 0, 1000003, 16): 3.182e7}
+def kernel_source_hash():
+    """SHA-256 over the library's device and host sources (csrc/), so a
+    counter figure can be matched to the kernel build it was taken on."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_1508_02512_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(poles, width, n, m):
+    """HBM bytes (read + written) per launch of one integrand kernel class of
+    this workload, from the rocprofv3 FETCH_SIZE and WRITE_SIZE passes
+    recorded in profiles/traffic.json (each calibrated with a 256 MiB device
+    copy).  None when no pass was taken for that class, or when the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None, "no counter record"
+    if rec.get("source_hash") != kernel_source_hash():
+        return None, "counters predate the current kernel sources"
+    for e in rec.get("entries", []):
+        if (e["poles"], e["width"], e["n"], e["m"]) == (poles, width, n, m):
+            return e["read_bytes"] + e["write_bytes"], "rocprofv3 FETCH_SIZE + WRITE_SIZE"
+    return None, "class not in the counter record"
 
 
 def parse():
@@ -117,13 +143,28 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=0.25)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-sectors", choices=("iterated", "geometric"), default="geometric")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     return ap.parse_args()
 
 
+def cpu_threads():
+    """Host threads the oracle may use: this process's CPU share, at most 16
+    (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def cpu_baseline(target_seconds):
-    """The oracle on a bounded sample of the same workload (all sectors,
-    small lattice, two shifts), all host cores."""
+    """The oracle on a bounded, stratified sample of the benchmark workload:
+    every 147th of the 882 sectors (6 sectors of several pole counts), 16
+    shifts, n = 100003.  Each sector call splits into 16 shifts x 2 chunks
+    of 2^16 indices = 32 jobs, so every thread has work.  The same sectors
+    at n = 10007 on one thread give the single-thread rate (the cost of one
+    evaluation does not depend on n), so the ratio of the two is the
+    parallel efficiency of the threads reported."""
     from oracle import qmc as oq
     from oracle.decompose import decompose as odec
     from seeded_inputs.lattice import lattice
@@ -133,28 +174,24 @@ def cpu_baseline(target_seconds):
     secs, info = odec(PROBLEMS["doublebox"])
     kin = {"s": -3.0, "t": -1.0}
     nums = [oq.NumericSector(s, info, kin) for s in secs]
-    n, m = 1009, 2
-    z, sh = lattice(n), shift_table(0, m, 8)
-    cores = os.cpu_count() or 1
-    evals = 0
-    t0 = time.perf_counter()
-    done = 0
-    for ns in nums:
-        oq.sector_sums(ns, n, z, sh, 2, 0.0, -4, 5, nthreads=cores)
-        evals += n * m
-        done += 1
-        if time.perf_counter() - t0 > target_seconds:
-            break
-    dt = time.perf_counter() - t0
-    # one thread, on a fifth of the time budget
-    ev1, done1, t1 = 0, 0, time.perf_counter()
-    for ns in nums:
-        oq.sector_sums(ns, n, z, sh, 2, 0.0, -4, 5, nthreads=1)
-        ev1 += n * m
-        done1 += 1
-        if time.perf_counter() - t1 > target_seconds / 5:
-            break
-    dt1 = time.perf_counter() - t1
+    m = 16
+    sh = shift_table(0, m, 8)
+    threads = cpu_threads()
+
+    def run(sample, n, nthreads, budget):
+        z = lattice(n)
+        evals, done, t0 = 0, 0, time.perf_counter()
+        for ns in sample:
+            oq.sector_sums(ns, n, z, sh, 2, 0.0, -4, 5, nthreads=nthreads)
+            evals += n * m
+            done += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return evals / (time.perf_counter() - t0), done
+
+    sample = nums[::147]
+    rate, done = run(sample, 100003, threads, target_seconds)
+    rate1, done1 = run(sample[:done], 10007, 1, target_seconds)
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -164,12 +201,13 @@ def cpu_baseline(target_seconds):
                     break
     except OSError:
         pass
-    return {"value": evals / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "single_thread_value": ev1 / dt1,
-            "single_thread_sample": f"first {done1} sectors, same n and m, 1 thread",
+    return {"value": rate, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": rate1,
+            "parallel_efficiency": rate / (threads * rate1),
+            "single_thread_sample": f"the same {done1} sectors, n=10007, m={m}, 1 thread",
             "cpu_model": model,
-            "sample": f"planar double box s=-3 t=-1, first {done} of {len(nums)} sectors, "
-                      f"n={n}, m={m} shifts, FP64 oracle, {cores} threads"}
+            "sample": f"planar double box s=-3 t=-1, {done} sectors (every 147th of "
+                      f"{len(nums)}), n=100003, m={m} shifts, FP64 oracle, {threads} threads"}
 
 
 # masses of Section IV (GeV^2) for the physical two-loop planar box I_C
@@ -532,6 +570,7 @@ def main():
                                       args.serve_rate, False, 1, log, args.serve_sectors),
         }
 
+    traffic, traffic_src = measured_traffic(dom_stat["poles"], dom_stat["width"], n, m)
     out = {
         "metric": METRIC,
         "value": value,
@@ -551,7 +590,7 @@ def main():
                    "evals_per_step": evals_per_step, "precision": "fp64"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
-                     "traffic": TRAFFIC_BYTES.get((dom_stat["poles"], dom_stat["width"], n, m)),
+                     "traffic": traffic, "traffic_source": traffic_src,
                      "kernel": f"qmc_eval_real<poles={dom_stat['poles']}, double>"
                                if dom_stat["width"] == 0 else
                                f"qmc_eval_cplx<width={dom_stat['width']}, "
