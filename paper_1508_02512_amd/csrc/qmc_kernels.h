@@ -26,3 +26,17 @@ hipError_t qmc_launch_reduce(const double *partial, const int32_t *viol,
 
 // qmc_math::ln, ln1p, ex, exm1 (fn = 0..3) applied to n device values.
 hipError_t qmc_launch_math(int fn, const double *x, double *y, long n, hipStream_t stream);
+
+// Serving: adds each step group's items (fixed order) into the request's
+// resident compensated sums dst[g][gks[g]][4]; per-group violation counts.
+hipError_t qmc_launch_serve_accumulate(const double *partial, const int32_t *viol,
+                                       const int32_t *group_begin, const int32_t *group_end,
+                                       double *const *dst, const int32_t *gks, int n_groups,
+                                       int kstride, int32_t *gviol, hipStream_t stream);
+// Serving: a request's sums [ns][m][kstride][4] combined over sectors per
+// shift and sector order: tot[m][n_orders][2].
+hipError_t qmc_launch_serve_combine(const double *sums, const qmc_sec_dev *sec, const double *D,
+                                    int ns, int m, int kstride, int n_orders, int sec_lo,
+                                    double inv_n, double *tot, hipStream_t stream);
+// p[0..n) = v.
+hipError_t qmc_launch_fill(double *p, long n, double v, hipStream_t stream);

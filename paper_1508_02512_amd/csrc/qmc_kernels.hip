@@ -90,3 +90,109 @@ hipError_t qmc_launch_math(int fn, const double *x, double *y, long n, hipStream
                        x, y, n);
     return hipGetLastError();
 }
+
+// Serving: the items of each group of one step summed in item order
+// (TwoSum), then added into the request's resident compensated sums:
+// dst[g][q] = (re hi, re lo, im hi, im lo) of order slot q < gks[g] (the
+// group's own slots; the step's partial slots may be wider).
+__global__ void qmc_serve_accumulate_k(const double *partial, const int32_t *viol,
+                                       const int32_t *group_begin, const int32_t *group_end,
+                                       double *const *dst, const int32_t *gks, int n_groups,
+                                       int kstride, int32_t *gviol)
+{
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = (int)(tid / kstride), q = (int)(tid % kstride);
+    if (g >= n_groups || q >= gks[g]) return;
+    const int i0 = group_begin[g], i1 = group_end[g];
+    double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+    int v = 0;
+    for (int i = i0; i < i1; ++i) {
+        const double *p = partial + ((size_t)i * kstride + q) * 4;
+        double e;
+        two_sum(sr, p[0], sr, e);
+        cr += p[1] + e;
+        two_sum(si, p[2], si, e);
+        ci += p[3] + e;
+        if (q == 0) v += viol[i];
+    }
+    double *d = dst[g] + (size_t)q * 4;
+    double s, e;
+    two_sum(d[0], sr, s, e);
+    d[1] += e + cr;
+    d[0] = s;
+    two_sum(d[2], si, s, e);
+    d[3] += e + ci;
+    d[2] = s;
+    if (q == 0) gviol[g] = v;
+}
+
+hipError_t qmc_launch_serve_accumulate(const double *partial, const int32_t *viol,
+                                       const int32_t *group_begin, const int32_t *group_end,
+                                       double *const *dst, const int32_t *gks, int n_groups,
+                                       int kstride, int32_t *gviol, hipStream_t stream)
+{
+    const long total = (long)n_groups * kstride;
+    if (total == 0) return hipSuccess;
+    const int threads = 256;
+    hipLaunchKernelGGL(qmc_serve_accumulate_k, dim3((unsigned)((total + threads - 1) / threads)),
+                       dim3(threads), 0, stream, partial, viol, group_begin, group_end, dst,
+                       gks, n_groups, kstride, gviol);
+    return hipGetLastError();
+}
+
+// Serving: one request's resident sums combined over sectors for every
+// shift k and sector Laurent order j (Eq. 19 before the prefactor):
+//   tot[k][j] = sum_s D_s (hi + lo)_{s,k,q} / n,  q = j + sec_lo + ks_s,
+// each sum compensated, sectors in index order.  One thread per (k, j).
+__global__ void qmc_serve_combine_k(const double *sums, const qmc_sec_dev *sec,
+                                    const double *D, int ns, int m, int kstride, int n_orders,
+                                    int sec_lo, double inv_n, double *tot)
+{
+    const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (tid >= m * n_orders) return;
+    const int k = tid / n_orders, j = tid % n_orders;
+    double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        const int q = j + sec_lo + sec[s].ks;
+        if (q < 0 || q >= sec[s].K) continue;
+        const double *p = sums + (((size_t)s * m + k) * kstride + q) * 4;
+        const double vr = (p[0] + p[1]) * inv_n, vi = (p[2] + p[3]) * inv_n;
+        const double dr = D[2 * s], di = D[2 * s + 1];
+        double e;
+        two_sum(sr, dr * vr - di * vi, sr, e);
+        cr += e;
+        two_sum(si, dr * vi + di * vr, si, e);
+        ci += e;
+    }
+    tot[2 * tid] = sr + cr;
+    tot[2 * tid + 1] = si + ci;
+}
+
+hipError_t qmc_launch_serve_combine(const double *sums, const qmc_sec_dev *sec, const double *D,
+                                    int ns, int m, int kstride, int n_orders, int sec_lo,
+                                    double inv_n, double *tot, hipStream_t stream)
+{
+    const int total = m * n_orders;
+    if (total == 0) return hipSuccess;
+    const int threads = 64;
+    hipLaunchKernelGGL(qmc_serve_combine_k, dim3((total + threads - 1) / threads),
+                       dim3(threads), 0, stream, sums, sec, D, ns, m, kstride, n_orders,
+                       sec_lo, inv_n, tot);
+    return hipGetLastError();
+}
+
+// Fills n doubles with v (graph-safe clearing; no memset node).
+__global__ void qmc_fill_k(double *p, long n, double v)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t qmc_launch_fill(double *p, long n, double v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int threads = 256;
+    hipLaunchKernelGGL(qmc_fill_k, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads),
+                       0, stream, p, n, v);
+    return hipGetLastError();
+}

@@ -1,17 +1,25 @@
 // Serving: continuous batching of integration requests.
 //
 // A scheduler thread per context admits queued requests (up to max_slots,
-// within the HBM budget) and repeatedly launches one batch that advances
-// every active request by one lattice size of its embedded rank-1 lattice
-// (Section III, Eq. 17): n0 first, then n -> 2n over the odd indices only,
-// since the points {2j z / 2n} of the even indices are the previous
-// lattice.  Requests of different plans, kinematic points and lattice sizes
-// share the launches of one batch (one launch per plan and kernel class).
-// Per-shift sums stay with the request; after every batch each request is
-// assembled (Eqs. 19-20) and retired once its error target is met.
+// within the HBM budget) and runs batch steps.  Each request integrates an
+// embedded rank-1 lattice (Section III, Eq. 17) level by level: n0 first,
+// then n -> 2n over the odd indices only, since the points {2j z / 2n} of
+// the even indices are the previous level.  A step advances every active
+// request by a fixed quota of its own work items (about 4M evaluations), so
+// a step, and the wait of a new arrival for admission, stays bounded; a
+// level may take several steps.
 //
-// A request's work items, tile sizes and summation order depend only on the
-// request itself, so its result is bitwise the same alone and in any mix.
+// Per-request state is resident on the device from admission to
+// retirement: the contracted coefficients, lambda per sector, the shifts
+// and the level's lattice rows (rows of slot-indexed pools), and the
+// compensated per-(sector, shift, order) sums, to which every step adds its
+// group sums in a fixed order.  When a level completes, a small kernel
+// combines the sectors per shift and only m x orders values come back for
+// the mean and error (Eqs. 19-20) and the convergence check.
+//
+// A request's work items, step windows and summation order depend only on
+// the request itself, so its result is bitwise the same alone and in any
+// mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +39,27 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
+// Work of one request in one batch step: at most this many integrand
+// evaluations (whole work items), so that a step, and hence the wait of a
+// newly arrived request for admission, stays bounded whatever the lattice
+// sizes of the requests already running.
+constexpr uint64_t STEP_EVALS = 1ull << 22;
+constexpr int MAX_SHIFTS = 64;           // shift rows per request slot
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Device rows of one plan, one per request slot: contracted coefficients,
+// derivative coefficients, per-sector lambda and per-sector lattices of the
+// request's current level; plus the sector constants D.
+struct PlanPool {
+    const qmc_plan *plan = nullptr;
+    DevBuf coef, dcoef, lam, lat, D;
+    int refs = 0;                        // active requests of the plan
+};
+
 struct Request {
     uint64_t ticket = 0;
     const qmc_plan *plan = nullptr;
@@ -43,7 +72,6 @@ struct Request {
     std::vector<double> coef, dcoef;     // contracted at the request's point
     std::vector<double> lam;             // [ns]
     std::vector<int> dm;                 // [ns] complex kernel width or 0
-    std::vector<double> hi, lo;          // running sums [ns][m][kstride][2]
     std::vector<qmc_coeff> coeff;        // current result
     uint64_t evals = 0;
     long violations = 0;
@@ -52,14 +80,16 @@ struct Request {
     int status = QMC_PENDING;
     bool cancelled = false, done = false;
     clk::time_point t_submit, t_done;
-    // this step
-    uint64_t step_n = 0, step_start = 0, step_stride = 1, step_count = 0, step_tile = 0;
-    int group_base = 0;
-};
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
+    // resident device state
+    int slot = -1;                       // row in the plan pool and shift pool
+    DevBuf sums;                         // [ns][m][kstride][4] compensated sums
+    size_t mem = 0;                      // bytes admitted for this request
+    // current level: n = level_n, indices start, start + stride, ...
+    uint64_t level_n = 0, level_start = 0, level_stride = 1, level_count = 0, tile = 0;
+    uint64_t items_per_group = 0, level_items = 0, cursor = 0;
+    bool level_fresh = true;             // lattice rows of this level not uploaded yet
+    long level_viol = 0;
+    std::vector<long> level_vsec;        // violations per sector in this level
 };
 
 } // namespace
@@ -75,27 +105,45 @@ struct qmc_serve_state {
     std::unordered_map<uint64_t, Request *> all;
     uint64_t next_ticket = 1;
     hipStream_t stream = nullptr;
-    std::map<std::string, DevBuf> bufs;
-    size_t pool_bytes = 0;
+    std::map<std::string, DevBuf> bufs;  // step buffers (grow-only)
+    std::map<const qmc_plan *, PlanPool> pools;
+    DevBuf shift_pool;                   // [max_slots][MAX_SHIFTS][QMC_DMAX]
+    std::vector<int> free_slots;
+    size_t pool_bytes = 0;               // device bytes of everything above
+    size_t fixed_bytes = 0;              // of which plan pools and the shift pool
+    size_t admitted = 0;                 // bytes admitted for active requests
 };
 
 namespace {
+
+int dev_alloc(qmc_serve_state *S, DevBuf &b, size_t bytes)
+{
+    b.p = nullptr;
+    b.bytes = 0;
+    if (bytes == 0) return QMC_OK;
+    int rc = qmc_dev_alloc(S->ctx, &b.p, bytes);
+    if (rc) return rc;
+    b.bytes = bytes;
+    S->pool_bytes += bytes;
+    return QMC_OK;
+}
+
+void dev_free(qmc_serve_state *S, DevBuf &b)
+{
+    if (!b.p) return;
+    qmc_dev_free(S->ctx, b.p, b.bytes);
+    S->pool_bytes -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+}
 
 int grow(qmc_serve_state *S, const char *name, size_t bytes, void **out)
 {
     DevBuf &b = S->bufs[name];
     if (b.bytes < bytes) {
-        if (b.p) {
-            qmc_dev_free(S->ctx, b.p, b.bytes);
-            S->pool_bytes -= b.bytes;
-            b.p = nullptr;
-            b.bytes = 0;
-        }
-        const size_t want = std::max(bytes, (size_t)4096) * 5 / 4;
-        int rc = qmc_dev_alloc(S->ctx, &b.p, want);
+        dev_free(S, b);
+        int rc = dev_alloc(S, b, std::max(bytes, (size_t)4096) * 5 / 4);
         if (rc) return rc;
-        b.bytes = want;
-        S->pool_bytes += want;
     }
     *out = b.p;
     return QMC_OK;
@@ -115,16 +163,45 @@ void splitmix_shifts(uint64_t seed, int m, std::vector<double> &out)
     }
 }
 
-// items (32 B) + partial slots + group sums of one step, plus rows
-size_t step_bytes(const Request *r, int kstride)
+// Lattice indices of the level at size n: all n of them for the first
+// level, else the n/2 odd ones (the even ones are the previous level).
+// Work items are tiles of 256 * ppl indices, ppl from the level's size.
+void level_shape(uint64_t n, bool first, uint64_t &start, uint64_t &stride, uint64_t &count,
+                 uint64_t &tile)
 {
-    const size_t ns = r->plan->secs.size();
-    const size_t groups = ns * r->m;
-    const size_t items = groups * 6;
-    return items * (sizeof(qmc_item) + (size_t)kstride * 32 + 4) +
-           groups * ((size_t)kstride * 16 + 12) +
-           (r->coef.size() + r->dcoef.size() + r->shifts.size() + ns) * 8 +
-           ns * sizeof(qmc_lat_dev) + (size_t)(r->plan->kstride) * ns * r->m * 32;
+    start = first ? 0 : 1;
+    stride = first ? 1 : 2;
+    count = first ? n : n / 2;
+    const uint64_t ppl = std::min<uint64_t>(
+        std::max<uint64_t>((count + QMC_BLOCK * 4 - 1) / (QMC_BLOCK * 4), 1), 1 << 14);
+    tile = (uint64_t)QMC_BLOCK * ppl;
+}
+
+// Items of one step for a request whose largest tile is `tile`
+uint64_t step_items(uint64_t tile) { return std::max<uint64_t>(STEP_EVALS / tile, 1); }
+
+// Device bytes a request holds while active: its resident sums plus its
+// largest share of the step buffers (items, partial slots, counters, group
+// ranges and destinations).  A step holds min(quota, items of the level) of
+// the request's items, maximised here over its levels n0 .. n_max.  Partial
+// slots are sized for the widest plan a step may mix (QMC_MAX_ORDERS).
+size_t request_bytes(const qmc_plan *P, int m, uint64_t n0, uint64_t n_max)
+{
+    const size_t ns = P->secs.size();
+    const size_t groups = ns * (size_t)m;
+    size_t items = 1;
+    for (uint64_t n = n0; n <= n_max; n *= 2) {
+        uint64_t st, sd, cnt, tile;
+        level_shape(n, n == n0, st, sd, cnt, tile);
+        const uint64_t level = (cnt + tile - 1) / tile * groups;
+        items = std::max<size_t>(items, (size_t)std::min(step_items(tile), level));
+    }
+    const size_t ks = (size_t)P->kstride;
+    // step buffers grow by a quarter beyond what they hold
+    const size_t step = items * (sizeof(qmc_item) + (size_t)QMC_MAX_ORDERS * 32 + 4) +
+                        items * (4 + 4 + 8 + 4 + 4) +          // group ranges, destinations
+                        (size_t)m * ks * 16;                   // combined totals
+    return groups * ks * 32 + step * 5 / 4 + 3 * 4096;
 }
 
 void finish(qmc_serve_state *S, Request *r, int status)
@@ -149,86 +226,231 @@ bool converged(const Request *r)
     return true;
 }
 
-// One batch over all active requests; returns a status for the whole batch.
-int run_step(qmc_serve_state *S, std::vector<Request *> &act)
+// Per-shift Laurent series (prefactor times the combined sector sums), then
+// mean and error over the shifts (Eqs. 19-20).  tot: [m][sector orders][2].
+void assemble_totals(const qmc_plan *P, int m, const std::vector<double> &tot,
+                     std::vector<qmc_coeff> &coeff)
+{
+    const int K = P->sec_hi - P->sec_lo + 1;
+    const int no = P->eps_hi - P->eps_lo + 1;
+    std::vector<std::complex<double>> Q((size_t)m * no);
+    for (int k = 0; k < m; ++k)
+        for (int oi = 0; oi < no; ++oi) {
+            const int order = P->eps_lo + oi;
+            std::complex<double> acc = 0.0;
+            for (int j = 0; j < K; ++j) {
+                const int pp = order - (P->sec_lo + j) - P->eps_pref_lo;
+                if (pp < 0 || pp >= P->n_pref) continue;
+                const std::complex<double> v(tot[((size_t)k * K + j) * 2],
+                                             tot[((size_t)k * K + j) * 2 + 1]);
+                acc += std::complex<double>(P->pref[2 * pp], P->pref[2 * pp + 1]) * v;
+            }
+            Q[(size_t)k * no + oi] = acc;
+        }
+    coeff.assign(no, qmc_coeff{});
+    for (int oi = 0; oi < no; ++oi) {
+        double mr = 0.0, mi = 0.0;
+        for (int k = 0; k < m; ++k) {
+            mr += Q[(size_t)k * no + oi].real();
+            mi += Q[(size_t)k * no + oi].imag();
+        }
+        mr /= m;
+        mi /= m;
+        double vr = 0.0, vi = 0.0;
+        for (int k = 0; k < m; ++k) {
+            const double dr = Q[(size_t)k * no + oi].real() - mr;
+            const double di = Q[(size_t)k * no + oi].imag() - mi;
+            vr += dr * dr;
+            vi += di * di;
+        }
+        coeff[oi] = {mr, mi, std::sqrt(vr / ((double)m * (m - 1))),
+                     std::sqrt(vi / ((double)m * (m - 1)))};
+    }
+}
+
+// Device bytes of a plan's pool (all slots) and of the shift pool.
+size_t plan_pool_bytes(const qmc_plan *P, int slots)
+{
+    const size_t ns = P->secs.size();
+    return (size_t)slots * (std::max(P->n_terms, 1) + std::max<size_t>(P->dexp.size(), 1) + ns) * 8 +
+           (size_t)slots * ns * sizeof(qmc_lat_dev) + ns * 16;
+}
+
+size_t shift_pool_bytes(int slots) { return (size_t)slots * MAX_SHIFTS * QMC_DMAX * 8; }
+
+// Device rows for a request at admission: plan pool (created on the plan's
+// first request), shift rows, resident sums.
+int admit_device(qmc_serve_state *S, Request *r)
+{
+    const qmc_plan *P = r->plan;
+    const int ns = (int)P->secs.size();
+    const int slots = S->ctx->max_slots;
+    hipStream_t st = S->stream;
+    if (!S->shift_pool.p) {
+        int rc = dev_alloc(S, S->shift_pool, shift_pool_bytes(slots));
+        if (rc) return rc;
+        S->fixed_bytes += S->shift_pool.bytes;
+        S->free_slots.clear();
+        for (int i = slots - 1; i >= 0; --i) S->free_slots.push_back(i);
+    }
+    auto it = S->pools.find(P);
+    if (it == S->pools.end()) {
+        PlanPool pp;
+        pp.plan = P;
+        int rc = dev_alloc(S, pp.coef, (size_t)slots * std::max(P->n_terms, 1) * 8);
+        if (!rc) rc = dev_alloc(S, pp.dcoef, (size_t)slots * std::max<size_t>(P->dexp.size(), 1) * 8);
+        if (!rc) rc = dev_alloc(S, pp.lam, (size_t)slots * ns * 8);
+        if (!rc) rc = dev_alloc(S, pp.lat, (size_t)slots * ns * sizeof(qmc_lat_dev));
+        if (!rc) rc = dev_alloc(S, pp.D, (size_t)ns * 16);
+        std::vector<double> D(2 * ns);
+        for (int s = 0; s < ns; ++s) {
+            D[2 * s] = P->secs[s].D.real();
+            D[2 * s + 1] = P->secs[s].D.imag();
+        }
+        if (!rc && hipMemcpyAsync(pp.D.p, D.data(), D.size() * 8, hipMemcpyHostToDevice, st) !=
+                       hipSuccess)
+            rc = QMC_EDEVICE;
+        // D is a local: wait for its upload before it goes out of scope
+        if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = QMC_EDEVICE;
+        if (rc) {
+            dev_free(S, pp.coef);
+            dev_free(S, pp.dcoef);
+            dev_free(S, pp.lam);
+            dev_free(S, pp.lat);
+            dev_free(S, pp.D);
+            return rc;
+        }
+        S->fixed_bytes += pp.coef.bytes + pp.dcoef.bytes + pp.lam.bytes + pp.lat.bytes + pp.D.bytes;
+        it = S->pools.emplace(P, pp).first;
+    }
+    if (S->free_slots.empty()) return QMC_EBUDGET;
+    int rc = dev_alloc(S, r->sums, (size_t)ns * r->m * P->kstride * 32);
+    if (rc) return rc;
+    r->slot = S->free_slots.back();
+    S->free_slots.pop_back();
+    it->second.refs += 1;
+    PlanPool &pp = it->second;
+    auto up = [&](void *base, size_t row_bytes, const void *src) {
+        return row_bytes ? hipMemcpyAsync((char *)base + (size_t)r->slot * row_bytes, src,
+                                          row_bytes, hipMemcpyHostToDevice, st)
+                         : hipSuccess;
+    };
+    hipError_t e = up(pp.coef.p, (size_t)P->n_terms * 8, r->coef.data());
+    if (e == hipSuccess) e = up(pp.dcoef.p, P->dexp.size() * 8, r->dcoef.data());
+    if (e == hipSuccess) e = up(pp.lam.p, (size_t)ns * 8, r->lam.data());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((char *)S->shift_pool.p + (size_t)r->slot * MAX_SHIFTS * QMC_DMAX * 8,
+                           r->shifts.data(), r->shifts.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = qmc_launch_fill((double *)r->sums.p, (long)(r->sums.bytes / 8), 0.0, st);
+    // the request's host rows stay alive while it is active, but a restart
+    // rewrites lam: keep the uploads ordered before any later host change
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
+}
+
+void release_device(qmc_serve_state *S, Request *r)
+{
+    if (r->slot < 0) return;
+    dev_free(S, r->sums);
+    S->free_slots.push_back(r->slot);
+    r->slot = -1;
+    auto it = S->pools.find(r->plan);
+    if (it != S->pools.end() && --it->second.refs == 0) {
+        PlanPool &pp = it->second;
+        S->fixed_bytes -= pp.coef.bytes + pp.dcoef.bytes + pp.lam.bytes + pp.lat.bytes + pp.D.bytes;
+        dev_free(S, pp.coef);
+        dev_free(S, pp.dcoef);
+        dev_free(S, pp.lam);
+        dev_free(S, pp.lat);
+        dev_free(S, pp.D);
+        S->pools.erase(it);
+    }
+    S->admitted -= r->mem;
+    r->mem = 0;
+}
+
+// Sets up the next level of a request (after admission, a completed level
+// or a restart).
+void start_level(Request *r)
+{
+    const bool first = r->n_cur == 0;
+    r->level_n = first ? r->n0 : 2 * r->n_cur;
+    level_shape(r->level_n, first, r->level_start, r->level_stride, r->level_count, r->tile);
+    r->items_per_group = (r->level_count + r->tile - 1) / r->tile;
+    r->level_items = r->items_per_group * r->plan->secs.size() * r->m;
+    r->cursor = 0;
+    r->level_fresh = true;
+    r->level_viol = 0;
+    r->level_vsec.assign(r->plan->secs.size(), 0);
+}
+
+// One batch step over all active requests: each advances by its own quota
+// of work items of its current level.  Returns a status for the whole step.
+int run_step(qmc_serve_state *S, std::vector<Request *> &act, std::vector<Request *> &done_lv)
 {
     qmc_ctx *ctx = S->ctx;
-    // lattice stage of every request
+    hipStream_t st = S->stream;
     int kstride = 1;
+    for (Request *r : act) kstride = std::max(kstride, r->plan->kstride);
+    // lattice rows of levels that start now
     for (Request *r : act) {
-        kstride = std::max(kstride, r->plan->kstride);
-        if (r->n_cur == 0) {
-            r->step_n = r->n0;
-            r->step_start = 0;
-            r->step_stride = 1;
-            r->step_count = r->n0;
-        } else {
-            r->step_n = 2 * r->n_cur;
-            r->step_start = 1;
-            r->step_stride = 2;
-            r->step_count = r->n_cur;
+        if (!r->level_fresh) continue;
+        const qmc_plan *P = r->plan;
+        const int ns = (int)P->secs.size();
+        std::vector<qmc_lat_dev> lats(ns);
+        for (int s = 0; s < ns; ++s) {
+            const qmc_sec_host &h = P->secs[s];
+            qmc_lat_dev d{};
+            d.n = (uint32_t)r->level_n;
+            d.inv_n = 1.0 / (double)r->level_n;
+            for (int j = 0; j < QMC_DMAX; ++j)
+                d.z[j] = j < h.dim ? (uint32_t)(r->z[h.perm[j]] % r->level_n) : 0u;
+            lats[s] = d;
         }
-        const uint64_t ppl = std::min<uint64_t>(
-            std::max<uint64_t>((r->step_count + QMC_BLOCK * 4 - 1) / (QMC_BLOCK * 4), 1), 1 << 14);
-        r->step_tile = (uint64_t)QMC_BLOCK * ppl;
+        PlanPool &pp = S->pools[P];
+        const size_t row = (size_t)ns * sizeof(qmc_lat_dev);
+        hipError_t e = hipMemcpyAsync((char *)pp.lat.p + (size_t)r->slot * row, lats.data(), row,
+                                      hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);       // lats is a local
+        if (e != hipSuccess)
+            return qmc_set_error(ctx, QMC_EDEVICE, "serving: %s", hipGetErrorString(e));
+        r->level_fresh = false;
     }
-    // requests by plan; rows of the per-plan input blocks
+    // this step's window [cursor, cursor + quota) of every request's level,
+    // items listed group-major; grouped into launches by (plan, class)
+    struct Win {
+        Request *r;
+        uint64_t begin, end;
+    };
+    std::vector<Win> wins;
+    for (Request *r : act) {
+        const uint64_t q = step_items(r->tile);
+        wins.push_back({r, r->cursor, std::min(r->cursor + q, r->level_items)});
+    }
     std::vector<const qmc_plan *> plans;
     for (Request *r : act)
         if (std::find(plans.begin(), plans.end(), r->plan) == plans.end()) plans.push_back(r->plan);
-    struct PlanBlock {
-        std::vector<Request *> reqs;
-        size_t coef_off = 0, dcoef_off = 0, shift_off = 0, lam_off = 0, lat_off = 0;
-    };
-    std::vector<PlanBlock> blocks(plans.size());
-    std::vector<double> coef, dcoef, shifts, lam;
-    std::vector<qmc_lat_dev> lats;
-    int groups = 0;
-    for (size_t pi = 0; pi < plans.size(); ++pi) {
-        PlanBlock &B = blocks[pi];
-        for (Request *r : act)
-            if (r->plan == plans[pi]) B.reqs.push_back(r);
-        B.coef_off = coef.size();
-        B.dcoef_off = dcoef.size();
-        B.shift_off = shifts.size();
-        B.lam_off = lam.size();
-        B.lat_off = lats.size();
-        for (Request *r : B.reqs) {
-            coef.insert(coef.end(), r->coef.begin(), r->coef.end());
-            dcoef.insert(dcoef.end(), r->dcoef.begin(), r->dcoef.end());
-            shifts.insert(shifts.end(), r->shifts.begin(), r->shifts.end());
-            lam.insert(lam.end(), r->lam.begin(), r->lam.end());
-            const int ns = (int)r->plan->secs.size();
-            for (int s = 0; s < ns; ++s) {
-                const qmc_sec_host &h = r->plan->secs[s];
-                qmc_lat_dev d{};
-                d.n = (uint32_t)r->step_n;
-                d.inv_n = 1.0 / (double)r->step_n;
-                for (int j = 0; j < QMC_DMAX; ++j)
-                    d.z[j] = j < h.dim ? (uint32_t)(r->z[h.perm[j]] % r->step_n) : 0u;
-                lats.push_back(d);
-            }
-            r->group_base = groups;
-            groups += ns * r->m;
-        }
-    }
-    // items grouped by (plan, kernel class)
     std::vector<qmc_item> items;
-    std::vector<int32_t> gbeg(groups), gend(groups);
+    std::vector<int32_t> gbeg, gend;
+    std::vector<double *> gdst;
+    std::vector<int32_t> gks;                      // order slots of each group's sums
+    std::vector<std::pair<Request *, int>> gown;   // (request, sector) of each step group
     struct Launch {
-        size_t plan;
+        const qmc_plan *plan;
         qmc_class cls;
     };
     std::vector<Launch> launches;
-    for (size_t pi = 0; pi < plans.size(); ++pi) {
-        const qmc_plan *P = plans[pi];
+    for (const qmc_plan *P : plans) {
         const int ns = (int)P->secs.size();
         std::vector<std::pair<int, int>> keys;
-        for (Request *r : blocks[pi].reqs)
+        for (const Win &w : wins) {
+            if (w.r->plan != P) continue;
             for (int s = 0; s < ns; ++s) {
-                std::pair<int, int> key{P->secs[s].ks, r->dm[s]};
+                std::pair<int, int> key{P->secs[s].ks, w.r->dm[s]};
                 if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
             }
+        }
         std::sort(keys.begin(), keys.end());
         for (const auto &key : keys) {
             qmc_class c{};
@@ -237,79 +459,76 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act)
             c.deform = c.dm != 0;
             c.kb = P->kb;
             c.begin = (int)items.size();
-            for (size_t row = 0; row < blocks[pi].reqs.size(); ++row) {
-                Request *r = blocks[pi].reqs[row];
-                for (int s = 0; s < ns; ++s) {
+            for (const Win &w : wins) {
+                Request *r = w.r;
+                if (r->plan != P || w.end <= w.begin) continue;
+                const uint64_t ipg = r->items_per_group;
+                const uint64_t g0 = w.begin / ipg, g1 = (w.end - 1) / ipg;
+                for (uint64_t g = g0; g <= g1; ++g) {
+                    const int s = (int)(g / r->m), k = (int)(g % r->m);
                     if (P->secs[s].ks != c.ks || r->dm[s] != c.dm) continue;
-                    for (int k = 0; k < r->m; ++k) {
-                        const int g = r->group_base + s * r->m + k;
-                        gbeg[g] = (int32_t)items.size();
-                        for (uint64_t off = 0; off < r->step_count; off += r->step_tile) {
-                            qmc_item it{};
-                            it.sector = s;
-                            it.point = (int32_t)row;
-                            it.shift = (int32_t)(row * r->m + k);
-                            it.group = g;
-                            it.lat = (int32_t)(row * ns + s);
-                            it.start = (uint32_t)(r->step_start + r->step_stride * off);
-                            it.count = (uint32_t)std::min<uint64_t>(r->step_tile,
-                                                                    r->step_count - off);
-                            it.stride = (uint32_t)r->step_stride;
-                            items.push_back(it);
-                        }
-                        gend[g] = (int32_t)items.size();
+                    gbeg.push_back((int32_t)items.size());
+                    const uint64_t i0 = std::max(w.begin, g * ipg), i1 = std::min(w.end, (g + 1) * ipg);
+                    for (uint64_t i = i0; i < i1; ++i) {
+                        const uint64_t off = (i - g * ipg) * r->tile;
+                        qmc_item it{};
+                        it.sector = s;
+                        it.point = r->slot;
+                        it.shift = r->slot * MAX_SHIFTS + k;
+                        it.group = (int32_t)gbeg.size() - 1;
+                        it.lat = r->slot * ns + s;
+                        it.start = (uint32_t)(r->level_start + r->level_stride * off);
+                        it.count = (uint32_t)std::min<uint64_t>(r->tile, r->level_count - off);
+                        it.stride = (uint32_t)r->level_stride;
+                        items.push_back(it);
+                        c.evals += it.count;
                     }
+                    gend.push_back((int32_t)items.size());
+                    gdst.push_back((double *)r->sums.p + ((size_t)(s * r->m + k) * P->kstride) * 4);
+                    gks.push_back(P->kstride);
+                    gown.push_back({r, s});
                 }
             }
             c.end = (int)items.size();
-            if (c.end > c.begin) launches.push_back({pi, c});
+            if (c.end > c.begin) launches.push_back({P, c});
         }
     }
-    // device buffers (grow-only pools) and uploads
-    void *d_items, *d_gbeg, *d_gend, *d_partial, *d_viol, *d_out, *d_gviol;
-    void *d_coef, *d_dcoef, *d_shift, *d_lam, *d_lat;
+    const int groups = (int)gbeg.size();
+    void *d_items, *d_gbeg, *d_gend, *d_gdst, *d_gks, *d_partial, *d_viol, *d_gviol;
     int rc = QMC_OK;
     rc = rc ? rc : grow(S, "items", items.size() * sizeof(qmc_item), &d_items);
-    rc = rc ? rc : grow(S, "gbeg", groups * 4, &d_gbeg);
-    rc = rc ? rc : grow(S, "gend", groups * 4, &d_gend);
+    rc = rc ? rc : grow(S, "gbeg", (size_t)groups * 4, &d_gbeg);
+    rc = rc ? rc : grow(S, "gend", (size_t)groups * 4, &d_gend);
+    rc = rc ? rc : grow(S, "gdst", (size_t)groups * 8, &d_gdst);
+    rc = rc ? rc : grow(S, "gks", (size_t)groups * 4, &d_gks);
     rc = rc ? rc : grow(S, "partial", items.size() * (size_t)kstride * 32, &d_partial);
     rc = rc ? rc : grow(S, "viol", items.size() * 4, &d_viol);
-    rc = rc ? rc : grow(S, "out", (size_t)groups * kstride * 16, &d_out);
-    rc = rc ? rc : grow(S, "gviol", groups * 4, &d_gviol);
-    rc = rc ? rc : grow(S, "coef", coef.size() * 8, &d_coef);
-    rc = rc ? rc : grow(S, "dcoef", dcoef.size() * 8, &d_dcoef);
-    rc = rc ? rc : grow(S, "shift", shifts.size() * 8, &d_shift);
-    rc = rc ? rc : grow(S, "lam", lam.size() * 8, &d_lam);
-    rc = rc ? rc : grow(S, "lat", lats.size() * sizeof(qmc_lat_dev), &d_lat);
+    rc = rc ? rc : grow(S, "gviol", (size_t)groups * 4, &d_gviol);
     if (rc) return rc;
-    hipStream_t st = S->stream;
     auto up = [&](void *dst, const void *src, size_t bytes) {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
     };
     hipError_t e = up(d_items, items.data(), items.size() * sizeof(qmc_item));
-    if (e == hipSuccess) e = up(d_gbeg, gbeg.data(), groups * 4);
-    if (e == hipSuccess) e = up(d_gend, gend.data(), groups * 4);
-    if (e == hipSuccess) e = up(d_coef, coef.data(), coef.size() * 8);
-    if (e == hipSuccess) e = up(d_dcoef, dcoef.data(), dcoef.size() * 8);
-    if (e == hipSuccess) e = up(d_shift, shifts.data(), shifts.size() * 8);
-    if (e == hipSuccess) e = up(d_lam, lam.data(), lam.size() * 8);
-    if (e == hipSuccess) e = up(d_lat, lats.data(), lats.size() * sizeof(qmc_lat_dev));
+    if (e == hipSuccess) e = up(d_gbeg, gbeg.data(), (size_t)groups * 4);
+    if (e == hipSuccess) e = up(d_gend, gend.data(), (size_t)groups * 4);
+    if (e == hipSuccess) e = up(d_gdst, gdst.data(), (size_t)groups * 8);
+    if (e == hipSuccess) e = up(d_gks, gks.data(), (size_t)groups * 4);
     for (const Launch &L : launches) {
         if (e != hipSuccess) break;
-        const qmc_plan *P = plans[L.plan];
-        const PlanBlock &B = blocks[L.plan];
+        const qmc_plan *P = L.plan;
+        PlanPool &pp = S->pools[P];
         qmc_launch_args A{};
         A.sec = P->d_sec;
-        A.lat = (const qmc_lat_dev *)d_lat + B.lat_off;
+        A.lat = (const qmc_lat_dev *)pp.lat.p;
         A.texp = P->d_texp;
         A.texpd = P->d_texpd;
         A.tprog = P->d_tprog;
         A.dprog = P->d_dprog;
-        A.tcoef = (const double *)d_coef + B.coef_off;
+        A.tcoef = (const double *)pp.coef.p;
         A.dexp = P->d_dexp;
-        A.dcoef = (const double *)d_dcoef + B.dcoef_off;
-        A.shifts = (const double *)d_shift + B.shift_off;
-        A.lam = (const double *)d_lam + B.lam_off;
+        A.dcoef = (const double *)pp.dcoef.p;
+        A.shifts = (const double *)S->shift_pool.p;
+        A.lam = (const double *)pp.lam.p;
         A.items = (const qmc_item *)d_items;
         A.partial = (double *)d_partial;
         A.viol = (int32_t *)d_viol;
@@ -323,62 +542,77 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act)
         e = qmc_launch_class(P, L.cls, A, st);
     }
     if (e == hipSuccess)
-        e = qmc_launch_reduce((const double *)d_partial, (const int32_t *)d_viol,
-                              (const int32_t *)d_gbeg, (const int32_t *)d_gend, groups, kstride,
-                              (double *)d_out, (int32_t *)d_gviol, st);
-    std::vector<double> out((size_t)groups * kstride * 2);
+        e = qmc_launch_serve_accumulate((const double *)d_partial, (const int32_t *)d_viol,
+                                        (const int32_t *)d_gbeg, (const int32_t *)d_gend,
+                                        (double *const *)d_gdst, (const int32_t *)d_gks, groups,
+                                        kstride, (int32_t *)d_gviol, st);
+    // the host arrays above are locals: the stream is drained below before
+    // they go out of scope
     std::vector<int32_t> gviol(groups);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(out.data(), d_out, out.size() * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(gviol.data(), d_gviol, groups * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && groups)
+        e = hipMemcpyAsync(gviol.data(), d_gviol, (size_t)groups * 4, hipMemcpyDeviceToHost, st);
+    // requests whose level completes in this step: combine their sums
+    done_lv.clear();
+    for (const Win &w : wins)
+        if (w.end >= w.r->level_items) done_lv.push_back(w.r);
+    std::vector<std::vector<double>> tots(done_lv.size());
+    for (size_t i = 0; i < done_lv.size() && e == hipSuccess; ++i) {
+        Request *r = done_lv[i];
+        const qmc_plan *P = r->plan;
+        const int K = P->sec_hi - P->sec_lo + 1;
+        void *d_tot;
+        char name[32];
+        snprintf(name, sizeof name, "tot%zu", i);
+        if (grow(S, name, (size_t)r->m * K * 16, &d_tot)) {
+            e = hipErrorOutOfMemory;
+            break;
+        }
+        e = qmc_launch_serve_combine((const double *)r->sums.p, P->d_sec,
+                                     (const double *)S->pools[P].D.p, (int)P->secs.size(), r->m,
+                                     P->kstride, K, P->sec_lo, 1.0 / (double)r->level_n,
+                                     (double *)d_tot, st);
+        tots[i].resize((size_t)r->m * K * 2);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(tots[i].data(), d_tot, tots[i].size() * 8, hipMemcpyDeviceToHost, st);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess)
         return qmc_set_error(ctx, QMC_EDEVICE, "serving step: %s", hipGetErrorString(e));
-    // fold the batch into every request and assemble
-    for (Request *r : act) {
-        const qmc_plan *P = r->plan;
-        const int ns = (int)P->secs.size();
-        r->evals += r->step_count * (uint64_t)ns * r->m;
+    // bookkeeping
+    for (const Win &w : wins) w.r->cursor = w.end;
+    for (size_t g = 0; g < (size_t)groups; ++g) {
+        Request *r = gown[g].first;
+        r->level_viol += gviol[g];
+        r->level_vsec[gown[g].second] += gviol[g];
+    }
+    for (size_t i = 0; i < done_lv.size(); ++i) {
+        Request *r = done_lv[i];
+        r->evals += r->level_count * (uint64_t)r->plan->secs.size() * r->m;
         r->steps += 1;
-        // sign violations of the deformed contour: back off lambda in the
-        // sectors concerned and restart the request while back-offs remain
-        std::vector<long> vsec(ns, 0);
-        long vtot = 0;
-        for (int s = 0; s < ns; ++s)
-            for (int k = 0; k < r->m; ++k) {
-                vsec[s] += gviol[r->group_base + s * r->m + k];
-                vtot += gviol[r->group_base + s * r->m + k];
-            }
-        if (vtot > 0 && r->halvings_left > 0) {
+        if (r->level_viol > 0 && r->halvings_left > 0) {
+            // back off lambda in the sectors concerned and restart at n0
+            const int ns = (int)r->plan->secs.size();
             for (int s = 0; s < ns; ++s)
-                if (vsec[s] > 0) r->lam[s] *= 0.5;
+                if (r->level_vsec[s] > 0) r->lam[s] *= 0.5;
             r->halvings_left -= 1;
             r->halvings += 1;
-            std::fill(r->hi.begin(), r->hi.end(), 0.0);
-            std::fill(r->lo.begin(), r->lo.end(), 0.0);
-            r->n_cur = 0;                    // the next step starts again at n0
+            PlanPool &pp = S->pools[r->plan];
+            hipError_t e2 = hipMemcpyAsync((char *)pp.lam.p + (size_t)r->slot * ns * 8,
+                                           r->lam.data(), (size_t)ns * 8,
+                                           hipMemcpyHostToDevice, st);
+            if (e2 == hipSuccess)
+                e2 = qmc_launch_fill((double *)r->sums.p, (long)(r->sums.bytes / 8), 0.0, st);
+            if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+            if (e2 != hipSuccess)
+                return qmc_set_error(ctx, QMC_EDEVICE, "serving: %s", hipGetErrorString(e2));
+            r->n_cur = 0;
+            r->coeff.assign(r->coeff.size(), qmc_coeff{});
+            start_level(r);
             continue;
         }
-        r->violations += vtot;
-        for (int s = 0; s < ns; ++s)
-            for (int k = 0; k < r->m; ++k) {
-                const int g = r->group_base + s * r->m + k;
-                for (int q = 0; q < P->kstride * 2; ++q) {
-                    const size_t o = ((size_t)(s * r->m + k) * P->kstride * 2) + q;
-                    const double x = out[(size_t)g * kstride * 2 + q];
-                    const double a = r->hi[o], sum = a + x, bb = sum - a;
-                    r->lo[o] += (a - (sum - bb)) + (x - bb);
-                    r->hi[o] = sum;
-                }
-            }
-        r->n_cur = r->step_n;
-        std::vector<double> gsum(r->hi.size());
-        for (size_t i = 0; i < gsum.size(); ++i) gsum[i] = r->hi[i] + r->lo[i];
-        std::vector<uint64_t> nsec(ns, r->n_cur);
-        qmc_result res{};
-        res.coeff = r->coeff.data();
-        qmc_assemble(P, 1, r->m, nsec, gsum.data(), &res);
+        r->violations += r->level_viol;
+        r->n_cur = r->level_n;
+        assemble_totals(r->plan, r->m, tots[i], r->coeff);
     }
     return QMC_OK;
 }
@@ -387,12 +621,14 @@ void scheduler(qmc_serve_state *S)
 {
     (void)hipSetDevice(S->ctx->device);
     std::unique_lock<std::mutex> lk(S->mu);
+    std::vector<Request *> done_lv;
     while (true) {
         S->cv.wait(lk, [&] { return S->stop || !S->pending.empty() || !S->active.empty(); });
         if (S->stop) break;
         // cancellations
         for (auto it = S->active.begin(); it != S->active.end();) {
             if ((*it)->cancelled) {
+                release_device(S, *it);
                 finish(S, *it, QMC_ECANCELLED);
                 it = S->active.erase(it);
             } else {
@@ -403,25 +639,40 @@ void scheduler(qmc_serve_state *S)
             finish(S, S->pending.front(), QMC_ECANCELLED);
             S->pending.pop_front();
         }
-        // admission by slots and device memory
-        size_t need = 0;
-        for (Request *r : S->active) need += step_bytes(r, QMC_MAX_ORDERS);
+        // admission by slots and device memory: a request holds at most
+        // request_bytes() beyond the plan pools while it is active
         while (!S->pending.empty() && (int)S->active.size() < S->ctx->max_slots) {
             Request *r = S->pending.front();
-            const size_t more = step_bytes(r, QMC_MAX_ORDERS);
-            const size_t other = S->ctx->used.load() - S->pool_bytes;
-            const size_t avail = S->ctx->budget > other ? S->ctx->budget - other : 0;
-            if (need + more > avail) {
-                if (S->active.empty()) {         // cannot fit even alone
-                    qmc_set_error(S->ctx, QMC_EBUDGET, "request %llu does not fit the budget",
+            // device memory outside serving, the pools, every active
+            // request's bound and this one's (with its plan's pool if new)
+            const int slots = S->ctx->max_slots;
+            size_t more = request_bytes(r->plan, r->m, r->n0, r->n_max);
+            if (!S->pools.count(r->plan)) more += plan_pool_bytes(r->plan, slots);
+            if (!S->shift_pool.p) more += shift_pool_bytes(slots);
+            const size_t used = S->ctx->used.load();
+            const size_t other = used > S->pool_bytes ? used - S->pool_bytes : 0;
+            const bool fits = other + S->fixed_bytes + S->admitted + more <= S->ctx->budget;
+            int rc = QMC_OK;
+            if (fits) {
+                lk.unlock();
+                rc = admit_device(S, r);
+                lk.lock();
+            }
+            if (!fits || rc != QMC_OK) {
+                if (r->slot >= 0) release_device(S, r);
+                if (S->active.empty() || rc == QMC_EDEVICE) {   // cannot fit even alone
+                    qmc_set_error(S->ctx, rc ? rc : QMC_EBUDGET,
+                                  "request %llu does not fit the budget",
                                   (unsigned long long)r->ticket);
-                    finish(S, r, QMC_EBUDGET);
+                    finish(S, r, rc ? rc : QMC_EBUDGET);
                     S->pending.pop_front();
                     continue;
                 }
                 break;
             }
-            need += more;
+            r->mem = request_bytes(r->plan, r->m, r->n0, r->n_max);
+            S->admitted += r->mem;
+            start_level(r);
             S->active.push_back(r);
             S->pending.pop_front();
         }
@@ -429,30 +680,51 @@ void scheduler(qmc_serve_state *S)
         if (S->active.empty()) continue;
         std::vector<Request *> act = S->active;
         lk.unlock();
-        const int rc = run_step(S, act);
+        int rc = run_step(S, act, done_lv);
         lk.lock();
+        if (rc == QMC_EBUDGET || rc == QMC_ENOMEM) {
+            // the step buffers did not fit: retire the newest request only
+            Request *r = S->active.back();
+            release_device(S, r);
+            qmc_set_error(S->ctx, rc, "request %llu retired: step buffers exceed the budget",
+                          (unsigned long long)r->ticket);
+            finish(S, r, rc);
+            S->active.pop_back();
+            S->done_cv.notify_all();
+            continue;
+        }
         for (auto it = S->active.begin(); it != S->active.end();) {
             Request *r = *it;
             bool retire = false;
+            const bool level_done =
+                std::find(done_lv.begin(), done_lv.end(), r) != done_lv.end();
             if (rc != QMC_OK) {
                 finish(S, r, rc);
                 retire = true;
-            } else if (r->violations > 0) {
-                finish(S, r, QMC_EDEFORM);
-                retire = true;
-            } else if (converged(r)) {
-                finish(S, r, QMC_OK);
-                retire = true;
-            } else if (2 * r->n_cur > r->n_max) {
-                finish(S, r, QMC_ENOTCONVERGED);
-                retire = true;
+            } else if (level_done && r->n_cur != 0) {
+                if (r->violations > 0) {
+                    finish(S, r, QMC_EDEFORM);
+                    retire = true;
+                } else if (converged(r)) {
+                    finish(S, r, QMC_OK);
+                    retire = true;
+                } else if (2 * r->n_cur > r->n_max) {
+                    finish(S, r, QMC_ENOTCONVERGED);
+                    retire = true;
+                } else {
+                    start_level(r);
+                }
             }
+            if (retire) release_device(S, r);
             it = retire ? S->active.erase(it) : it + 1;
         }
         S->done_cv.notify_all();
     }
     // drain
-    for (Request *r : S->active) finish(S, r, QMC_ECANCELLED);
+    for (Request *r : S->active) {
+        release_device(S, r);
+        finish(S, r, QMC_ECANCELLED);
+    }
     for (Request *r : S->pending) finish(S, r, QMC_ECANCELLED);
     S->active.clear();
     S->pending.clear();
@@ -507,7 +779,8 @@ void qmc_serve_shutdown(qmc_ctx *ctx)
     S->cv.notify_all();
     if (S->th.joinable()) S->th.join();
     for (auto &kv : S->all) delete kv.second;
-    for (auto &kv : S->bufs) qmc_dev_free(ctx, kv.second.p, kv.second.bytes);
+    for (auto &kv : S->bufs) dev_free(S, kv.second);
+    dev_free(S, S->shift_pool);
     if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
     ctx->serve = nullptr;
@@ -518,7 +791,8 @@ extern "C" int qmc_submit(qmc_ctx *ctx, const qmc_plan *plan, const qmc_request 
 {
     if (!ctx || !plan || !req || !ticket || !req->kin || !req->z)
         return qmc_set_error(ctx, QMC_EINVAL, "null argument");
-    if (req->m < 2) return qmc_set_error(ctx, QMC_EINVAL, "need m >= 2 shifts");
+    if (req->m < 2 || req->m > MAX_SHIFTS)
+        return qmc_set_error(ctx, QMC_EINVAL, "need 2 <= m <= %d shifts", MAX_SHIFTS);
     auto pow2 = [](uint64_t v) { return v >= 2 && (v & (v - 1)) == 0; };
     if (!pow2(req->n0) || !pow2(req->n_max) || req->n0 > req->n_max ||
         req->n_max >= (1ull << 31))
@@ -550,8 +824,6 @@ extern "C" int qmc_submit(qmc_ctx *ctx, const qmc_plan *plan, const qmc_request 
     r->lam.resize(ns);
     r->dm.resize(ns);
     for (int s = 0; s < ns; ++s) r->dm[s] = qmc_sector_mode(plan, s, r->coef.data(), &r->lam[s]);
-    r->hi.assign((size_t)ns * r->m * plan->kstride * 2, 0.0);
-    r->lo.assign(r->hi.size(), 0.0);
     r->coeff.assign(plan->eps_hi - plan->eps_lo + 1, qmc_coeff{});
     r->t_submit = clk::now();
     {

@@ -111,6 +111,29 @@ def test_budget_too_small():
     small.close()
 
 
+def test_large_request_runs_in_bounded_steps_beside_small_ones():
+    """A request that doubles to n = 2^25 (past 2^24, where a level needs
+    more work items than one step takes) shares a context with a tight
+    budget (64 MiB) with small requests submitted after it: each step takes
+    only a bounded window of the large request's items, so the small ones
+    are admitted and finish first, and the large one ends at n_max
+    (QMC_ENOTCONVERGED), neither refused nor failing the others."""
+    print("serve: bounded steps, one large and six small requests", flush=True)
+    small_ctx = qmc.Context(0, hbm_budget=64 << 20)
+    secs, info = fe.decompose(__import__("seeded_inputs.problems", fromlist=["x"]).PROBLEMS["box"])
+    plan = small_ctx.plan(fe.sector_arrays(secs, info), info, 0, fe.prefactor_series(info, 8))
+    big = qmc.submit(plan, _box_kin(info), 1e-300, 1 << 10, 1 << 25, 4, 5, Z)
+    smalls = [qmc.submit(plan, _box_kin(info, -2.0 - 0.1 * i, -1.5), 1e-4, 1 << 10, 1 << 16,
+                         4, 40 + i, Z) for i in range(6)]
+    rs = [x.wait(300) for x in smalls]
+    rb = big.wait(300)
+    assert rb["rc"] == -7 and rb["n_final"] == 1 << 25, rb["rc"]
+    assert all(r["rc"] == 0 for r in rs)
+    assert max(r["latency_ms"] for r in rs) < rb["latency_ms"]
+    plan.close()
+    small_ctx.close()
+
+
 def test_deformation_violation_reported():
     print("serve: lambda too large", flush=True)
     plan, info = gpu_plan("np_vertex", lam=1.0)
