@@ -64,6 +64,15 @@ extern "C" {
 /* ---- precision modes ----------------------------------------------------- */
 #define QMC_FP64 0               /* all arithmetic in FP64 */
 #define QMC_FP32_EVAL 1          /* FP32 integrand, FP64 where stability needs it */
+/* FP32_EVAL: periodiser, monomials, U and F, the Moebius algebra and the
+ * eps series of Euclidean sectors in FP32; for deformed sectors the power
+ * table, derivative terms, z and the complex monomials of U(z), F(z) in
+ * FP32, the Jacobian determinant and the logarithms/powers of U and F in
+ * FP64; lattice points, corner differences and all sums in FP64.  The
+ * Eq. 20 error does not include the FP32 rounding bias (measured up to
+ * 2.7e-6 relative on the double box); serving requests on FP32_EVAL plans
+ * must ask for rel_err_target >= QMC_FP32_TARGET_FLOOR. */
+#define QMC_FP32_TARGET_FLOOR 1e-5
 
 typedef struct qmc_ctx qmc_ctx;     /* device, stream, budget, scheduler */
 typedef struct qmc_plan qmc_plan;   /* device-resident sector tables */

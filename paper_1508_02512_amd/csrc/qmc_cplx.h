@@ -11,6 +11,13 @@
 // in the other variables, so every corner is a full evaluation).  The
 // Jacobian determinant comes from an LDL^T factorisation of a complex
 // symmetric matrix similar to dz/dt (see leaf()).
+//
+// T is the evaluation type of the polynomial work: double (QMC_FP64) or
+// float (QMC_FP32_EVAL).  In float mode the power table, the gradient and
+// Hessian terms of F, the deformed point z and the complex monomials of
+// U(z) and F(z) are FP32; the Jacobian determinant, the logarithms and
+// powers of U and F (F can come close to 0 on the contour), the eps series,
+// the corner differences and the accumulation stay FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -68,38 +75,62 @@ __device__ __forceinline__ cd cexp_(cd x)
     return {e * c, e * s};
 }
 
+// complex numbers in the evaluation type
+template <typename T>
+struct cx {
+    T r, i;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> xmul(cx<T> a, cx<T> b)
+{
+    return {fma(a.r, b.r, -a.i * b.i), fma(a.r, b.i, a.i * b.r)};
+}
+
+template <typename T>
+__device__ __forceinline__ cd widen(cx<T> a)
+{
+    return {(double)a.r, (double)a.i};
+}
+
+// log(1 + q^2) / 2 and atan(q) in the evaluation type
+__device__ __forceinline__ double half_log1p_sq(double q) { return 0.5 * qmc_math::ln1p(q * q); }
+__device__ __forceinline__ float half_log1p_sq(float q) { return 0.5f * log1pf(q * q); }
+__device__ __forceinline__ double atan_t(double q) { return atan(q); }
+__device__ __forceinline__ float atan_t(float q) { return atanf(q); }
+
 // prod_j z_j^e_j for 4-bit wave-uniform exponents, powers formed on the fly
 // (no tables of z^2, z^3: the leaf's register budget goes to the Jacobian)
-template <int DM>
-__device__ __forceinline__ cd cmonomial(uint32_t e, const cd *z)
+template <int DM, typename T>
+__device__ __forceinline__ cx<T> cmonomial(uint32_t e, const cx<T> *z)
 {
-    cd v = {1.0, 0.0};
+    cx<T> v = {T(1), T(0)};
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
         const uint32_t ej = (e >> (4 * j)) & 15u;
         if (ej == 0u) continue;
-        cd p = z[j];
+        cx<T> p = z[j];
         if (ej >= 2u) {
-            const cd z2 = cmul(z[j], z[j]);
-            p = ej == 2u ? z2 : cmul(z2, ej == 3u ? z[j] : z2);
-            for (uint32_t k = 4u; k < ej; ++k) p = cmul(p, z[j]);
+            const cx<T> z2 = xmul(z[j], z[j]);
+            p = ej == 2u ? z2 : xmul(z2, ej == 3u ? z[j] : z2);
+            for (uint32_t k = 4u; k < ej; ++k) p = xmul(p, z[j]);
         }
-        v = cmul(v, p);
+        v = xmul(v, p);
     }
     return v;
 }
 
-template <int DM>
-__device__ __forceinline__ double rmonomial(uint32_t e, const double *t)
+template <int DM, typename T>
+__device__ __forceinline__ T rmonomial(uint32_t e, const T *t)
 {
-    double v = 1.0;
+    T v = 1;
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
         const uint32_t ej = (e >> (4 * j)) & 15u;
         if (ej == 0u) continue;
-        double p = t[j];
+        T p = t[j];
         if (ej >= 2u) {
-            const double t2 = t[j] * t[j];
+            const T t2 = t[j] * t[j];
             p = ej == 2u ? t2 : t2 * (ej == 3u ? t[j] : t2);
             for (uint32_t k = 4u; k < ej; ++k) p *= t[j];
         }
@@ -108,19 +139,19 @@ __device__ __forceinline__ double rmonomial(uint32_t e, const double *t)
     return v;
 }
 
-template <int DM, int KS, int K>
+template <int DM, int KS, int K, typename T>
 struct CplxPoint;
 
 // derivative term q at the corner's real point: power-table product, or the
 // branchy product of powers for terms with more than eight factors
-template <int DM, int KS, int K>
-__device__ __forceinline__ double dmono(const CplxPoint<DM, KS, K> &P, int q, const double *tp)
+template <int DM, int KS, int K, typename T>
+__device__ __forceinline__ T dmono(const CplxPoint<DM, KS, K, T> &P, int q, const T *tp)
 {
-    return (P.dprog[2 * q] >> 31) ? rmonomial<DM>(P.dexp[q], tp)
-                                  : tmono_lds<double>(P.dprog + 2 * q, P.col);
+    return (P.dprog[2 * q] >> 31) ? rmonomial<DM, T>(P.dexp[q], tp)
+                                  : tmono_lds<T>(P.dprog + 2 * q, P.col);
 }
 
-template <int DM, int KS, int K>
+template <int DM, int KS, int K, typename T>
 struct CplxPoint {
     double t[DM], omt[DM], lt[DM];
     double invt[KS > 0 ? KS : 1];
@@ -130,25 +161,25 @@ struct CplxPoint {
     cptr<double> dcoef;              // derivative coefficients at this point
     cptr<uint32_t> texp, dexp;
     cptr<uint32_t> dprog;            // derivative terms as power-table words
-    double *col;                     // this lane's column of the power table
+    T *col;                          // this lane's column of the power table
     double lam;                      // deformation parameter of this sector and point
     int bad;
 };
 
 // h at corner X (pole variables in X set to 0), deformed, as a series
-template <int DM, int KS, int K>
-__device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &P, int X,
+template <int DM, int KS, int K, typename T>
+__device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K, T> &P, int X,
                                      cd (&h)[K])
 {
-    double tp[DM], op[DM];
+    T tp[DM], op[DM];
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
         const bool zero = j < KS && ((X >> j) & 1);
-        tp[j] = zero ? 0.0 : P.t[j];
-        op[j] = zero ? 1.0 : P.omt[j];
+        tp[j] = zero ? T(0) : T(P.t[j]);
+        op[j] = zero ? T(1) : T(P.omt[j]);
     }
     const int d = S->dim;
-    const double lam = P.lam;
+    const T lam = T(P.lam);
     // powers of this corner's real point for the derivative terms (only
     // the lane itself reads its column)
 #pragma unroll
@@ -159,18 +190,18 @@ __device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &
         }
     }
     // gradient of F at the real point
-    double g[DM];
+    T g[DM];
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
-        double s = 0.0;
+        T s = 0;
         if (j < d)
             for (int q = S->d1[j]; q < S->d1[j + 1]; ++q)
-                s = fma(P.dcoef[q], dmono<DM>(P, q, tp), s);
+                s = fma(T(P.dcoef[q]), dmono<DM, KS, K, T>(P, q, tp), s);
         g[j] = s;
     }
     // q_j = lambda (1 - t_j) g_j, phi_j = 1 - i q_j, z_j = t_j phi_j
-    double qv[DM];
-    cd z[DM];
+    T qv[DM];
+    cx<T> z[DM];
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
         qv[j] = lam * op[j] * g[j];
@@ -183,25 +214,25 @@ __device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &
     // A real symmetric: I + i A is complex symmetric with identity real
     // part, so an LDL^T factorisation without pivoting is stable.  Its lower
     // triangle is packed row by row; rows beyond the sector's dimension are
-    // identity.
-    double sj[DM];
+    // identity.  The factorisation is FP64 in both modes.
+    T sj[DM];
 #pragma unroll
-    for (int j = 0; j < DM; ++j) sj[j] = j < d ? sqrt(lam * tp[j] * op[j]) : 0.0;
+    for (int j = 0; j < DM; ++j) sj[j] = j < d ? sqrt(lam * tp[j] * op[j]) : T(0);
     constexpr int NT = DM * (DM + 1) / 2;
     cd J[NT];
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
 #pragma unroll
         for (int k = 0; k <= j; ++k) {
-            double hs = 0.0;
+            T hs = 0;
             if (j < d) {
                 const int idx = k * QMC_DMAX - k * (k - 1) / 2 + (j - k);
                 for (int q = S->d2[idx]; q < S->d2[idx + 1]; ++q)
-                    hs = fma(P.dcoef[q], dmono<DM>(P, q, tp), hs);
+                    hs = fma(T(P.dcoef[q]), dmono<DM, KS, K, T>(P, q, tp), hs);
             }
-            double a = -(sj[j] * hs) * sj[k];
+            T a = -(sj[j] * hs) * sj[k];
             if (j == k && j < d) a -= lam * (op[j] - tp[j]) * g[j];
-            J[j * (j + 1) / 2 + k] = {j == k ? 1.0 : 0.0, a};
+            J[j * (j + 1) / 2 + k] = {j == k ? 1.0 : 0.0, (double)a};
         }
     }
     cd det = {1.0, 0.0};
@@ -218,19 +249,21 @@ __device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &
                 J[r * (r + 1) / 2 + k] = csub(J[r * (r + 1) / 2 + k], cmul(f, J[k * (k + 1) / 2 + c]));
         }
     }
-    // U(z), F(z)
-    cd U = {0.0, 0.0}, F = {0.0, 0.0};
+    // U(z), F(z) in the evaluation type
+    cx<T> Ut = {T(0), T(0)}, Ft = {T(0), T(0)};
     for (int q = S->um[0]; q < S->um[QMC_NMASK]; ++q) {
-        const cd v = cmonomial<DM>(P.texp[q], z);
-        U.r = fma(P.coef[q], v.r, U.r);
-        U.i = fma(P.coef[q], v.i, U.i);
+        const cx<T> v = cmonomial<DM, T>(P.texp[q], z);
+        Ut.r = fma(T(P.coef[q]), v.r, Ut.r);
+        Ut.i = fma(T(P.coef[q]), v.i, Ut.i);
     }
     for (int q = S->fm[0]; q < S->fm[QMC_NMASK]; ++q) {
-        const cd v = cmonomial<DM>(P.texp[q], z);
-        F.r = fma(P.coef[q], v.r, F.r);
-        F.i = fma(P.coef[q], v.i, F.i);
+        const cx<T> v = cmonomial<DM, T>(P.texp[q], z);
+        Ft.r = fma(T(P.coef[q]), v.r, Ft.r);
+        Ft.i = fma(T(P.coef[q]), v.i, Ft.i);
     }
-    P.bad |= (F.i > 0.0) | !(U.r > 0.0);
+    P.bad |= (Ft.i > T(0)) | !(Ut.r > T(0));
+    // logarithms and powers of U and F in FP64
+    const cd U = widen(Ut), F = widen(Ft);
     const cd lU = clog_m(U), lF = clog_m(F);
     cd pre;
     if (S->u0i != QMC_NO_INT && S->f0i != QMC_NO_INT)
@@ -242,15 +275,15 @@ __device__ __forceinline__ void leaf(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &
     L.r += P.LN;
 #pragma unroll
     for (int j = 0; j < DM; ++j) {
-        if (j >= d || qv[j] == 0.0) continue;
+        if (j >= d || qv[j] == T(0)) continue;
         // Log phi_j = 1/2 log(1 + q^2) - i atan(q)
-        const cd lphi = {0.5 * qmc_math::ln1p(qv[j] * qv[j]), -atan(qv[j])};
+        const cd lphi = {(double)half_log1p_sq(qv[j]), -(double)atan_t(qv[j])};
         L = cadd(L, cscale(lphi, S->b[j]));
         const int ai = j < KS ? -1 : S->aint[j];
         if (ai == QMC_NO_INT)
             pre = cmul(pre, cexp_(cscale(lphi, S->a[j])));
         else if (ai != 0)
-            pre = cmul(pre, cpowi(cd{1.0, -qv[j]}, ai));
+            pre = cmul(pre, cpowi(cd{1.0, -(double)qv[j]}, ai));
     }
     h[0] = pre;
 #pragma unroll
@@ -279,14 +312,14 @@ __device__ __forceinline__ void cfold(cd (&A)[K], const cd (&B)[K], double invb,
 // All corners of the pole variables in a runtime loop (the deformed leaf is
 // large, so it is instantiated once); partial folds wait on a stack whose
 // levels are unrolled: corner X completes level l when bit l of X is set.
-template <int DM, int KS, int K>
-__device__ __forceinline__ void corners_folded(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K> &P,
+template <int DM, int KS, int K, typename T>
+__device__ __forceinline__ void corners_folded(cptr<qmc_sec_dev> S, CplxPoint<DM, KS, K, T> &P,
                                                cd (&out)[K])
 {
     cd stack[KS > 0 ? KS : 1][K];
     for (int X = 0; X < (1 << KS); ++X) {
         cd cur[K];
-        leaf<DM, KS, K>(S, P, X, cur);
+        leaf<DM, KS, K, T>(S, P, X, cur);
         bool carry = true;
 #pragma unroll
         for (int lev = 0; lev < KS; ++lev) {
@@ -312,9 +345,9 @@ __device__ __forceinline__ void corners_folded(cptr<qmc_sec_dev> S, CplxPoint<DM
 }
 
 // One work item (a tile of one (point, sector, shift) group).
-template <int DM, int KS, int K>
+template <int DM, int KS, int K, typename T>
 __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, const int item_id,
-                                                   double *col)
+                                                   T *col)
 {
     const qmc_item it = load_item(A.items, item_id);
     cptr<qmc_sec_dev> S = ro(A.sec) + it.sector;
@@ -348,7 +381,7 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
     for (int p = 0; p < np; ++p) {
         const uint32_t off = threadIdx.x + (uint32_t)p * QMC_BLOCK;
         if (off < it.count) {
-            CplxPoint<DM, KS, K> P;
+            CplxPoint<DM, KS, K, T> P;
             P.coef = ro(A.tcoef) + (size_t)it.point * A.n_terms;
             P.dcoef = ro(A.dcoef) + (size_t)it.point * A.n_dterms;
             P.texp = ro(A.texp);
@@ -399,7 +432,7 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
                 }
                 P.LN = LN;
                 cd g[K];
-                corners_folded<DM, KS, K>(S, P, g);
+                corners_folded<DM, KS, K, T>(S, P, g);
                 if (P.bad) {
                     viol += 1;
                 } else {
@@ -442,25 +475,25 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
 // scratch for that; measured on the gg -> HH double boxes and the
 // non-planar vertex, one wave per SIMD (no spills) is 3.1x slower, two
 // 1.9x, three 1.2x, six about the same, eight 1.15x.
-template <int DM, int KS, int K>
+template <int DM, int KS, int K, typename T>
 __global__ __launch_bounds__(QMC_BLOCK)
 __attribute__((amdgpu_waves_per_eu(4, 8))) void qmc_eval_cplx(qmc_launch_args A)
 {
     // per-lane power table of the corner points (slot layout as in the
     // real kernel, last slot the constant 1)
-    __shared__ double pw[QMC_PROG_SLOTS * QMC_BLOCK];
-    pw[(QMC_PROG_SLOTS - 1) * QMC_BLOCK + threadIdx.x] = 1.0;
+    __shared__ T pw[QMC_PROG_SLOTS * QMC_BLOCK];
+    pw[(QMC_PROG_SLOTS - 1) * QMC_BLOCK + threadIdx.x] = T(1);
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
-        qmc_eval_cplx_item<DM, KS, K>(A, item, pw + threadIdx.x);
+        qmc_eval_cplx_item<DM, KS, K, T>(A, item, pw + threadIdx.x);
         __syncthreads();
     }
 }
 
 } // namespace qmc_cplx
 
-#define QMC_CPLX_CASE(DM, KS, KB)                                                  \
+#define QMC_CPLX_CASE(DM, KS, KB, T)                                               \
     if (ks == KS && kb == KB) {                                                    \
-        hipLaunchKernelGGL((qmc_cplx::qmc_eval_cplx<DM, KS, KS + KB>), dim3(grid),  \
+        hipLaunchKernelGGL((qmc_cplx::qmc_eval_cplx<DM, KS, KS + KB, T>), dim3(grid), \
                            dim3(QMC_BLOCK), 0, stream, args);                      \
         return hipGetLastError();                                                  \
     }

@@ -623,7 +623,9 @@ hipError_t qmc_launch_class(const qmc_plan *plan, const qmc_class &c, const qmc_
                             hipStream_t stream)
 {
     const int grid = qmc_class_grid(c);
-    if (c.deform) return qmc_launch_cplx(c.dm, c.ks, c.kb, A, grid, stream);
+    if (c.deform)
+        return qmc_launch_cplx(c.dm, c.ks, c.kb, plan->opts.precision == QMC_FP32_EVAL, A, grid,
+                               stream);
     return qmc_launch_real(c.ks, c.kb, plan->opts.precision == QMC_FP32_EVAL, A, grid, stream);
 }
 

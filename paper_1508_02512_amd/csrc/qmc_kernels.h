@@ -11,10 +11,11 @@
 hipError_t qmc_launch_real(int ks, int kb, bool fp32, const qmc_launch_args &args, int grid,
                            hipStream_t stream);
 
-// Complex FP64 integrand with contour deformation (Eq. 14) for sectors of
-// dimension <= dm (dm = qmc_cplx_dm(dim)).
-hipError_t qmc_launch_cplx(int dm, int ks, int kb, const qmc_launch_args &args, int grid,
-                           hipStream_t stream);
+// Complex integrand with contour deformation (Eq. 14) for sectors of
+// dimension <= dm (dm = qmc_cplx_dm(dim)); polynomial work in FP32 when
+// fp32, else FP64.
+hipError_t qmc_launch_cplx(int dm, int ks, int kb, bool fp32, const qmc_launch_args &args,
+                           int grid, hipStream_t stream);
 int qmc_cplx_dm(int dim);
 bool qmc_cplx_supported(int dim, int ks, int kb);
 

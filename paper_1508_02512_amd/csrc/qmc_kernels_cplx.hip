@@ -7,6 +7,12 @@ hipError_t qmc_launch_cplx4(int ks, int kb, const qmc_launch_args &args, int gri
                             hipStream_t stream);
 hipError_t qmc_launch_cplx6(int ks, int kb, const qmc_launch_args &args, int grid,
                             hipStream_t stream);
+hipError_t qmc_launch_cplx2_f32(int ks, int kb, const qmc_launch_args &args, int grid,
+                                hipStream_t stream);
+hipError_t qmc_launch_cplx4_f32(int ks, int kb, const qmc_launch_args &args, int grid,
+                                hipStream_t stream);
+hipError_t qmc_launch_cplx6_f32(int ks, int kb, const qmc_launch_args &args, int grid,
+                                hipStream_t stream);
 
 int qmc_cplx_dm(int dim) { return dim <= 2 ? 2 : dim <= 4 ? 4 : dim <= 6 ? 6 : 0; }
 
@@ -21,12 +27,15 @@ bool qmc_cplx_supported(int dim, int ks, int kb)
     return dm != 0 && ks >= 0 && ks <= 2 && kb >= 1 && kb <= (dm == 2 ? 3 : 2);
 }
 
-hipError_t qmc_launch_cplx(int dm, int ks, int kb, const qmc_launch_args &args, int grid,
-                           hipStream_t stream)
+hipError_t qmc_launch_cplx(int dm, int ks, int kb, bool fp32, const qmc_launch_args &args,
+                           int grid, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
-    if (dm == 2) return qmc_launch_cplx2(ks, kb, args, grid, stream);
-    if (dm == 4) return qmc_launch_cplx4(ks, kb, args, grid, stream);
-    if (dm == 6) return qmc_launch_cplx6(ks, kb, args, grid, stream);
+    if (dm == 2) return fp32 ? qmc_launch_cplx2_f32(ks, kb, args, grid, stream)
+                             : qmc_launch_cplx2(ks, kb, args, grid, stream);
+    if (dm == 4) return fp32 ? qmc_launch_cplx4_f32(ks, kb, args, grid, stream)
+                             : qmc_launch_cplx4(ks, kb, args, grid, stream);
+    if (dm == 6) return fp32 ? qmc_launch_cplx6_f32(ks, kb, args, grid, stream)
+                             : qmc_launch_cplx6(ks, kb, args, grid, stream);
     return hipErrorInvalidValue;
 }

@@ -72,3 +72,55 @@ def test_fp32_four_poles_next_to_the_corner():
         scale = abss[..., 0] + abss[..., 1]
         assert np.all(np.abs(gpu - sums) <= 1e-5 * scale), s
     plan.close()
+
+
+@pytest.mark.parametrize("name,kin,lam,strategy", [
+    ("hh_planar", None, 1.0, "geometric"),
+    ("np_vertex", {"s": 4.5, "msq": 1.0}, 0.5, "iterated"),
+    ("box", {"s": 3.0, "t": -2.0}, 0.5, "iterated"),
+])
+def test_fp32_deformed_sectors(name, kin, lam, strategy):
+    """Deformed sectors in the FP32-eval mode (FP32 power table, derivative
+    terms, z and complex monomials; FP64 Jacobian determinant, logs and
+    powers of U and F, series, corner differences and sums): every sampled
+    sector within 1e-5 of sum |w g| of the FP64 oracle (measured: 4e-7 on
+    the gg -> HH planar box, 7e-8 on the non-planar vertex)."""
+    from seeded_inputs.problems import HH_POINT
+    kin = HH_POINT if kin is None else kin
+    print(f"fp32 deformed {name} lambda={lam}", flush=True)
+    sectors = None if name == "box" else sample_sectors(name, per_class=6, strategy=strategy)
+    res, _ = compare_sectors(name, kin, 1009, 2, lam=lam, tol=1e-5, precision=FP32,
+                             quad_from=99, strategy=strategy, sectors=sectors)
+    assert res["violations"] == 0
+
+
+def test_fp32_deformed_whole_result_within_error():
+    """I_C (Section IV.C) on its geometric sectors at n = 131071, 16 shifts:
+    the FP32-eval result lies within three of its stated errors of the FP64
+    result, order by order, and both meet the 1e-3 level."""
+    from seeded_inputs.problems import HH_POINT
+    print("fp32 vs fp64 I_C n=131071 m=16", flush=True)
+    p64, info = gpu_plan("hh_planar", lam=1.0, strategy="geometric")
+    p32, _ = gpu_plan("hh_planar", lam=1.0, strategy="geometric", precision=FP32)
+    args = (fe.kin_vector(info, HH_POINT), (131071, lattice(131071)), shift_table(0, 16, 8))
+    a, b = p64.integrate(*args), p32.integrate(*args)
+    err32 = np.hypot(b["err_re"][0], b["err_im"][0])
+    assert np.all(np.abs(b["mean"][0] - a["mean"][0]) <= 3 * err32)
+    assert np.all(err32 / np.abs(a["mean"][0]) < 1e-3)
+    p64.close()
+    p32.close()
+
+
+def test_fp32_serving_target_floor():
+    """FP32-eval plans carry a rounding bias (measured up to 2.7e-6 relative
+    on the double box); serving requests asking for less than 1e-5 on such
+    a plan are refused."""
+    from seeded_inputs.lattice import lattice as lat
+    plan, info = gpu_plan("box", precision=FP32)
+    kin = fe.kin_vector(info, {"s": -3.0, "t": -2.0})
+    with pytest.raises(qmc.QMCError) as e:
+        qmc.submit(plan, kin, 1e-6, 1 << 10, 1 << 16, 4, 1, lat(1 << 24))
+    assert e.value.code == -1
+    r = qmc.submit(plan, kin, 1e-5, 1 << 10, 1 << 16, 4, 1, lat(1 << 24)).wait(60)
+    assert r["rc"] in (0, -7)
+    plan.close()
