@@ -91,10 +91,11 @@ hipError_t qmc_launch_math(int fn, const double *x, double *y, long n, hipStream
     return hipGetLastError();
 }
 
-// Serving: the items of each group of one step summed in item order
-// (TwoSum), then added into the request's resident compensated sums:
+// Serving: the items of each group of one step added, one at a time in item
+// order, into the request's resident compensated sums (TwoSum):
 // dst[g][q] = (re hi, re lo, im hi, im lo) of order slot q < gks[g] (the
-// group's own slots; the step's partial slots may be wider).
+// group's own slots; the step's partial slots may be wider).  Adding item by
+// item makes the sums independent of how a level's items are cut into steps.
 __global__ void qmc_serve_accumulate_k(const double *partial, const int32_t *viol,
                                        const int32_t *group_begin, const int32_t *group_end,
                                        double *const *dst, const int32_t *gks, int n_groups,
@@ -104,25 +105,22 @@ __global__ void qmc_serve_accumulate_k(const double *partial, const int32_t *vio
     const int g = (int)(tid / kstride), q = (int)(tid % kstride);
     if (g >= n_groups || q >= gks[g]) return;
     const int i0 = group_begin[g], i1 = group_end[g];
-    double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+    double *d = dst[g] + (size_t)q * 4;
+    double hr = d[0], lr = d[1], hi = d[2], li = d[3];
     int v = 0;
     for (int i = i0; i < i1; ++i) {
         const double *p = partial + ((size_t)i * kstride + q) * 4;
         double e;
-        two_sum(sr, p[0], sr, e);
-        cr += p[1] + e;
-        two_sum(si, p[2], si, e);
-        ci += p[3] + e;
+        two_sum(hr, p[0], hr, e);
+        lr += e + p[1];
+        two_sum(hi, p[2], hi, e);
+        li += e + p[3];
         if (q == 0) v += viol[i];
     }
-    double *d = dst[g] + (size_t)q * 4;
-    double s, e;
-    two_sum(d[0], sr, s, e);
-    d[1] += e + cr;
-    d[0] = s;
-    two_sum(d[2], si, s, e);
-    d[3] += e + ci;
-    d[2] = s;
+    d[0] = hr;
+    d[1] = lr;
+    d[2] = hi;
+    d[3] = li;
     if (q == 0) gviol[g] = v;
 }
 

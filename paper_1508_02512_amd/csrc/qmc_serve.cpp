@@ -5,7 +5,7 @@
 // embedded rank-1 lattice (Section III, Eq. 17) level by level: n0 first,
 // then n -> 2n over the odd indices only, since the points {2j z / 2n} of
 // the even indices are the previous level.  A step advances every active
-// request by a fixed quota of its own work items (about 4M evaluations), so
+// request by an equal share of a fixed work budget (2^26 evaluations), so
 // a step, and the wait of a new arrival for admission, stays bounded; a
 // level may take several steps.
 //
@@ -13,13 +13,13 @@
 // retirement: the contracted coefficients, lambda per sector, the shifts
 // and the level's lattice rows (rows of slot-indexed pools), and the
 // compensated per-(sector, shift, order) sums, to which every step adds its
-// group sums in a fixed order.  When a level completes, a small kernel
+// work items one by one in item order.  When a level completes, a small kernel
 // combines the sectors per shift and only m x orders values come back for
 // the mean and error (Eqs. 19-20) and the convergence check.
 //
-// A request's work items, step windows and summation order depend only on
-// the request itself, so its result is bitwise the same alone and in any
-// mix.
+// A request's work items and their summation order depend only on the
+// request itself (not on how its levels are cut into steps, which depends
+// on the load), so its result is bitwise the same alone and in any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,11 +39,14 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
-// Work of one request in one batch step: at most this many integrand
-// evaluations (whole work items), so that a step, and hence the wait of a
-// newly arrived request for admission, stays bounded whatever the lattice
-// sizes of the requests already running.
-constexpr uint64_t STEP_EVALS = 1ull << 22;
+// Work of one batch step: at most this many integrand evaluations (whole
+// work items), shared evenly by the active requests, so that a step, and
+// hence the wait of a newly arrived request for admission, stays bounded
+// whatever the lattice sizes of the requests already running.  Work items
+// are tiles of SERVE_TILE lattice indices (32 per lane), small enough that a
+// step has thousands of work-groups.
+constexpr uint64_t STEP_EVALS = 1ull << 26;
+constexpr uint64_t SERVE_TILE = (uint64_t)QMC_BLOCK * 32;
 constexpr int MAX_SHIFTS = 64;           // shift rows per request slot
 
 struct DevBuf {
@@ -165,20 +168,20 @@ void splitmix_shifts(uint64_t seed, int m, std::vector<double> &out)
 
 // Lattice indices of the level at size n: all n of them for the first
 // level, else the n/2 odd ones (the even ones are the previous level).
-// Work items are tiles of 256 * ppl indices, ppl from the level's size.
 void level_shape(uint64_t n, bool first, uint64_t &start, uint64_t &stride, uint64_t &count,
                  uint64_t &tile)
 {
     start = first ? 0 : 1;
     stride = first ? 1 : 2;
     count = first ? n : n / 2;
-    const uint64_t ppl = std::min<uint64_t>(
-        std::max<uint64_t>((count + QMC_BLOCK * 4 - 1) / (QMC_BLOCK * 4), 1), 1 << 14);
-    tile = (uint64_t)QMC_BLOCK * ppl;
+    tile = SERVE_TILE;
 }
 
-// Items of one step for a request whose largest tile is `tile`
-uint64_t step_items(uint64_t tile) { return std::max<uint64_t>(STEP_EVALS / tile, 1); }
+// Items one request may take in a step when `active` requests share it
+uint64_t step_items(uint64_t tile, size_t active)
+{
+    return std::max<uint64_t>(STEP_EVALS / (tile * std::max<size_t>(active, 1)), 1);
+}
 
 // Device bytes a request holds while active: its resident sums plus its
 // largest share of the step buffers (items, partial slots, counters, group
@@ -194,7 +197,7 @@ size_t request_bytes(const qmc_plan *P, int m, uint64_t n0, uint64_t n_max)
         uint64_t st, sd, cnt, tile;
         level_shape(n, n == n0, st, sd, cnt, tile);
         const uint64_t level = (cnt + tile - 1) / tile * groups;
-        items = std::max<size_t>(items, (size_t)std::min(step_items(tile), level));
+        items = std::max<size_t>(items, (size_t)std::min(step_items(tile, 1), level));
     }
     const size_t ks = (size_t)P->kstride;
     // step buffers grow by a quarter beyond what they hold
@@ -425,7 +428,7 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act, std::vector<Reques
     };
     std::vector<Win> wins;
     for (Request *r : act) {
-        const uint64_t q = step_items(r->tile);
+        const uint64_t q = step_items(r->tile, act.size());
         wins.push_back({r, r->cursor, std::min(r->cursor + q, r->level_items)});
     }
     std::vector<const qmc_plan *> plans;
@@ -799,6 +802,10 @@ extern "C" int qmc_submit(qmc_ctx *ctx, const qmc_plan *plan, const qmc_request 
         return qmc_set_error(ctx, QMC_EINVAL, "n0 <= n_max must be powers of two below 2^31");
     if (!(req->rel_err_target > 0.0))
         return qmc_set_error(ctx, QMC_EINVAL, "rel_err_target must be positive");
+    if (plan->opts.precision == QMC_FP32_EVAL && req->rel_err_target < QMC_FP32_TARGET_FLOOR)
+        return qmc_set_error(ctx, QMC_EINVAL,
+                             "FP32-eval plans: rel_err_target must be >= %g (rounding bias)",
+                             QMC_FP32_TARGET_FLOOR);
     if (req->lambda_halvings < 0 || req->lambda_halvings > 16)
         return qmc_set_error(ctx, QMC_EINVAL, "lambda_halvings must be in 0..16");
     for (int j = 0; j < QMC_DMAX; ++j)
