@@ -136,8 +136,8 @@ def parse():
     ap.add_argument("--no-time-to-target", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--extra", action="store_true",
-                    help="also run the non-planar vertex and the 512-point batch")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the non-planar vertex, the 512-point batch and the s-scan")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM counters)")
     ap.add_argument("--serve-rate", type=float, default=200.0,
@@ -348,24 +348,49 @@ def serve_suite(qmc, fe, PROBLEMS, lattice, args, log):
     return out
 
 
-def vertex_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, n_total=10000019):
+def launch_roofline(job, peak=PEAK_FP64_VALU):
+    """One eager, profiled run of a bound job: the dominant kernel-class
+    launch (the longest), its algorithmic flops over its HIP-event time,
+    against the vector peak."""
+    job.profile(True)
+    job.run()
+    r = job.fetch()
+    st = job.class_stats()
+    dom = max(st, key=lambda c: c["ms"])
+    achieved = dom["algo_flops"] / (dom["ms"] / 1e3)
+    job.profile(False)
+    kind = (f"qmc_eval_real<poles={dom['poles']}>" if dom["width"] == 0 else
+            f"qmc_eval_cplx<width={dom['width']}, poles={dom['poles']}>")
+    return {"bound": "alu", "kernel": kind, "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / peak, "launch_ms": dom["ms"],
+            "points_per_lane": dom["points_per_lane"], "grid": dom["grid"],
+            "occupancy_variant": dom["variant"],
+            "step_kernel_ms": r["kernel_ms"],
+            "step_frac": r["algo_flops"] / (r["kernel_ms"] / 1e3) / peak}, r
+
+
+def sizing_primes(lo, hi):
+    from seeded_inputs.lattice import PRIME_SIZES
+    return [p for p in PRIME_SIZES if lo <= p <= hi]
+
+
+def vertex_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, n_avg=10000019):
     """Non-planar two-loop vertex with a massive loop, s = 4.5 (physical),
-    lambda = 0.5, 32 shifts, per-sector lattice sizes from a pilot run."""
-    import numpy as np
+    lambda = 0.5, 32 shifts, per-sector lattice sizes from the library's
+    variance-weighted sizing (pilot at n = 65521) for an average of
+    n_avg points per sector."""
     import torch
 
-    from seeded_inputs.lattice import PRIME_SIZES
     secs, info = fe.decompose(PROBLEMS["np_vertex"])
     plan = ctx.plan(fe.sector_arrays(secs, info), info, 0, fe.prefactor_series(info, 12),
                     lam=0.5)
     kin = fe.kin_vector(info, {"s": 4.5, "msq": 1.0})
     sh = shift_table(0, 32, 8)
-    sizes = qmc.size_lattices(plan, kin, n_total * plan.n_sectors, PRIME_SIZES, 65521,
-                              lattice(65521), shift_table(1, 8, 8))
+    sizes = qmc.size_lattices(plan, kin, n_avg * plan.n_sectors, sizing_primes(10007, 10 ** 8),
+                              65521, lattice(65521), shift_table(1, 8, 8))
     lats = [(n, lattice(n)) for n in sizes]
     job = plan.bind(kin, None, sh, lat_per_sector=lats)
-    job.run()
-    job.fetch()
+    roof, _ = launch_roofline(job)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     job.run()
@@ -373,12 +398,16 @@ def vertex_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, n_total=1000
     wall = time.perf_counter() - t0
     job.close()
     plan.close()
-    out = {"value": r["evals"] / wall, "unit": "evals/s", "seconds": wall,
-           "kernel_ms": r["kernel_ms"], "achieved_tflops": r["algo_flops"] / r["kernel_ms"] / 1e9,
+    out = {"workload": "non-planar two-loop vertex, massive loop, s=4.5, lambda=0.5, "
+                       "32 shifts, variance-weighted sector lattices",
+           "value": r["evals"] / wall, "unit": "evals/s", "seconds": wall,
+           "evals": r["evals"], "kernel_ms": r["kernel_ms"],
+           "achieved_tflops": r["algo_flops"] / r["kernel_ms"] / 1e9,
            "eps0": [float(r["mean"][0, -1].real), float(r["mean"][0, -1].imag)],
            "err": [float(r["err_re"][0, -1]), float(r["err_im"][0, -1])],
-           "violations": int(r["violations"]), "n_min": min(sizes), "n_max": max(sizes)}
-    log(f"np_vertex: {out['value']:.3e} evals/s, eps^0 = {out['eps0']} +- {out['err']}")
+           "violations": int(r["violations"]), "n_min": min(sizes), "n_max": max(sizes),
+           "n_mean": sum(sizes) / len(sizes), "roofline": roof}
+    log(f"np_vertex: {out['value']:.3e} evals/s, dominant launch {roof['frac']:.3f} of peak")
     return out
 
 
@@ -420,8 +449,11 @@ def hh_box_scan(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log):
 def batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, fp32):
     """512 kinematic points of the all-massive two-loop planar vertex,
     s uniform in [-10, 10] without |s - 4| < 0.05 (numpy PCG64 seed 0),
-    every sector with its own lattice size (100003 .. 10000019), one
-    autotuned, graph-replayed launch sequence."""
+    geometric sectors, 4 shifts, every sector with its own lattice size in
+    [1e5, 1e7] from the library's variance-weighted sizing at s = 6 (average
+    1e6 points per sector); launch shapes (points per lane, persistent grid,
+    occupancy build) from the autotuner; the whole launch sequence captured
+    in one HIP graph and replayed."""
     import numpy as np
     import torch
 
@@ -431,16 +463,19 @@ def batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, fp32):
         v = float(rng.uniform(-10.0, 10.0))
         if abs(v - 4.0) >= 0.05:
             svals.append(v)
-    secs, info = fe.decompose(PROBLEMS["triangle2l"])
+    secs, info = fe.decompose(PROBLEMS["triangle2l"], "geometric")
     prec = qmc.QMC_FP32_EVAL if fp32 else qmc.QMC_FP64
     plan = ctx.plan(fe.sector_arrays(secs, info), info, 0, fe.prefactor_series(info, 12),
                     lam=0.25, precision=prec)
     kin = np.stack([fe.kin_vector(info, {"s": v, "msq": 1.0}) for v in svals])
-    tiers = [100003, 1000003, 10000019]
-    lats = [(n, lattice(n)) for n in (tiers[i % 3] for i in range(plan.n_sectors))]
+    sizes = qmc.size_lattices(plan, fe.kin_vector(info, {"s": 6.0, "msq": 1.0}),
+                              10 ** 6 * plan.n_sectors, sizing_primes(10 ** 5, 10 ** 7), 65521,
+                              lattice(65521), shift_table(1, 8, 8))
+    lats = [(n, lattice(n)) for n in sizes]
     sh = shift_table(0, 4, 8)
     choices = plan.autotune(kin[:8], None, shift_table(0, 2, 8), lat_per_sector=lats)
     job = plan.bind(kin, None, sh, lat_per_sector=lats)
+    roof, _ = launch_roofline(job)
     job.use_graph(True)
     job.run()
     job.fetch()
@@ -451,10 +486,14 @@ def batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, fp32):
     wall = time.perf_counter() - t0
     job.close()
     plan.close()
-    out = {"value": r["evals"] / wall, "unit": "evals/s", "seconds": wall,
+    out = {"workload": "two-loop massive planar vertex, 512 points s in [-10, 10], 22 "
+                       "geometric sectors, uneven lattices, 4 shifts, one graph replay",
+           "value": r["evals"] / wall, "unit": "evals/s", "seconds": wall, "evals": r["evals"],
            "precision": "fp32-eval" if fp32 else "fp64", "points": len(svals),
-           "autotune": choices, "violations": int(r["violations"])}
-    log(f"batch ({out['precision']}): {out['value']:.3e} evals/s in {wall:.2f} s")
+           "n_min": min(sizes), "n_max": max(sizes), "autotune": choices,
+           "violations": int(r["violations"]), "roofline": roof}
+    log(f"batch ({out['precision']}): {out['value']:.3e} evals/s in {wall:.2f} s, "
+        f"dominant launch {roof['frac']:.3f} of peak")
     return out
 
 
@@ -596,14 +635,13 @@ def main():
         plan32.close()
         log(f"fp32: {fp32['value']:.3e} evals/s")
 
-    extra = None
-    if args.extra:
-        extra = {"np_vertex": vertex_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log),
-                 "hh_box_scan": hh_box_scan(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log),
-                 "batch_fp64": batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log,
-                                           False),
-                 "batch_fp32": batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log,
-                                           True)}
+    workloads = None
+    if not args.no_workloads:
+        workloads = {
+            "np_vertex": vertex_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log),
+            "batch_fp64": batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, False),
+            "batch_fp32": batch_bench(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log, True),
+            "hh_box_scan": hh_box_scan(qmc, fe, PROBLEMS, lattice, shift_table, ctx, log)}
 
     paper = None
     if not args.no_time_to_target:
@@ -655,7 +693,7 @@ def main():
         "fp32_eval": fp32,
         "paper_workloads_time_to_1e-3": paper,
         "serve": serve,
-        "extra": extra,
+        "workloads": workloads,
         "result_eps0": [float(res["mean"][0, -1].real), float(res["err_re"][0, -1])],
     }
     if not args.no_cpu_baseline:

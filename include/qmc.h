@@ -178,6 +178,23 @@ int qmc_integrate(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
                   const qmc_lattice *lat_per_sector, const double *shifts,
                   int32_t m, qmc_result *out);
 
+/* Per-sector lattice sizes for a total budget of lattice points (uneven
+ * sizing across sectors, the sizing of Section III's error estimate applied
+ * per sector).  A pilot integration at the kinematic point kin[n_inv] on
+ * the lattice `pilot` with shifts[m][QMC_MAX_DIM] gives each sector's spread
+ * c_s over the shifts (largest over orders and real/imaginary parts of
+ * |S_k/n - mean_k S_k/n|).  With a lattice error ~ c_s / n_s and a cost
+ * proportional to the sector's algorithmic flops f_s per point, minimising
+ * sum_s (c_s / n_s)^2 at fixed sum_s f_s n_s gives n_s ~ (c_s^2 / f_s)^(1/3);
+ * the sizes are scaled so that sum_s n_s = total_points and each is rounded,
+ * in log scale, to the nearest of sizes[n_sizes] (the caller's lattices).
+ * out_n[n_sectors] receives the chosen sizes.  Errors: QMC_EINVAL on bad
+ * sizes or pointers; those of qmc_integrate for the pilot. */
+int qmc_size_lattices(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
+                      const qmc_lattice *pilot, const double *shifts, int32_t m,
+                      uint64_t total_points, const uint64_t *sizes, int32_t n_sizes,
+                      uint64_t *out_n);
+
 /* ---- allocation-free variant ------------------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.
@@ -222,13 +239,17 @@ void qmc_job_free(qmc_job *job);
  * qmc_autotune: times candidate launch shapes on the given inputs (which
  * should have the lattice sizes of the production runs; two shifts are
  * enough) and remembers, per (plan, poles, kernel width, lattice-size
- * octave), the fastest points-per-lane and persistent-grid setting.  Later
+ * octave), the fastest points per lane (the length of each lane's point
+ * loop), persistent-grid setting and occupancy build (waves per SIMD).  Later
  * binds with points_per_lane = 0 use them.  choices (may be NULL) receives
  * up to max_choices entries; *n_choices is set to the number of classes. */
 typedef struct {
     int32_t poles, width;        /* kernel class: poles, complex width (0 = real) */
     int32_t points_per_lane;     /* chosen tile: 256 * points_per_lane indices per item */
     int32_t grid_per_cu;         /* 0: one work-group per item; else persistent */
+    int32_t occupancy_variant;   /* 0: build with the swept waves per SIMD; 1: the build
+                                    with fewer waves (real kernels one fewer, deformed 2) */
+    int32_t pad;
     double ms;                   /* measured time of the class with that shape */
 } qmc_tune_choice;
 
@@ -254,6 +275,8 @@ typedef struct {
     uint64_t evals;              /* integrand evaluations of one launch */
     double algo_flops;           /* algorithmic flops of one launch */
     double ms;                   /* launch time of the last eager run, or -1 */
+    int32_t variant;             /* occupancy build launched (see qmc_tune_choice) */
+    int32_t pad;
 } qmc_class_stat;
 
 int qmc_job_set_profiling(qmc_job *job, int enable);

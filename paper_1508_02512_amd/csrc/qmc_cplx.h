@@ -475,9 +475,11 @@ __device__ __forceinline__ void qmc_eval_cplx_item(const qmc_launch_args &A, con
 // scratch for that; measured on the gg -> HH double boxes and the
 // non-planar vertex, one wave per SIMD (no spills) is 3.1x slower, two
 // 1.9x, three 1.2x, six about the same, eight 1.15x.
-template <int DM, int KS, int K, typename T>
+// Occupancy variant 1 builds for two waves (far fewer spills); the
+// autotuner chooses per workload.
+template <int DM, int KS, int K, typename T, int V>
 __global__ __launch_bounds__(QMC_BLOCK)
-__attribute__((amdgpu_waves_per_eu(4, 8))) void qmc_eval_cplx(qmc_launch_args A)
+__attribute__((amdgpu_waves_per_eu(V == 0 ? 4 : 2, 8))) void qmc_eval_cplx(qmc_launch_args A)
 {
     // per-lane power table of the corner points (slot layout as in the
     // real kernel, last slot the constant 1)
@@ -491,9 +493,9 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void qmc_eval_cplx(qmc_launch_args A)
 
 } // namespace qmc_cplx
 
-#define QMC_CPLX_CASE(DM, KS, KB, T)                                               \
+#define QMC_CPLX_CASE(DM, KS, KB, T, V)                                            \
     if (ks == KS && kb == KB) {                                                    \
-        hipLaunchKernelGGL((qmc_cplx::qmc_eval_cplx<DM, KS, KS + KB, T>), dim3(grid), \
+        hipLaunchKernelGGL((qmc_cplx::qmc_eval_cplx<DM, KS, KS + KB, T, V>), dim3(grid), \
                            dim3(QMC_BLOCK), 0, stream, args);                      \
         return hipGetLastError();                                                  \
     }

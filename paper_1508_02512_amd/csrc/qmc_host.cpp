@@ -623,10 +623,9 @@ hipError_t qmc_launch_class(const qmc_plan *plan, const qmc_class &c, const qmc_
                             hipStream_t stream)
 {
     const int grid = qmc_class_grid(c);
-    if (c.deform)
-        return qmc_launch_cplx(c.dm, c.ks, c.kb, plan->opts.precision == QMC_FP32_EVAL, A, grid,
-                               stream);
-    return qmc_launch_real(c.ks, c.kb, plan->opts.precision == QMC_FP32_EVAL, A, grid, stream);
+    const bool fp32 = plan->opts.precision == QMC_FP32_EVAL;
+    if (c.deform) return qmc_launch_cplx(c.dm, c.ks, c.kb, fp32, c.variant, A, grid, stream);
+    return qmc_launch_real(c.ks, c.kb, fp32, c.variant, A, grid, stream);
 }
 
 void qmc_job_release(qmc_job *job)
@@ -774,6 +773,7 @@ int qmc_job_prepare(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32
             if (t != ctx->tuned.end()) {
                 c.ppl = t->second.ppl;
                 c.grid = t->second.grid_per_cu * ctx->n_cu;
+                c.variant = t->second.variant;
             }
         }
         const uint64_t tile = (uint64_t)QMC_BLOCK * c.ppl;
@@ -1105,6 +1105,62 @@ extern "C" int qmc_integrate(qmc_ctx *ctx, const qmc_plan *plan, const double *k
     return rc;
 }
 
+extern "C" int qmc_size_lattices(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
+                                 const qmc_lattice *pilot, const double *shifts, int32_t m,
+                                 uint64_t total_points, const uint64_t *sizes, int32_t n_sizes,
+                                 uint64_t *out_n)
+{
+    if (!ctx || !plan || !kin || !pilot || !shifts || !sizes || !out_n || n_sizes < 1)
+        return set_err(ctx, QMC_EINVAL, "qmc_size_lattices: null argument or no sizes");
+    for (int i = 0; i < n_sizes; ++i)
+        if (sizes[i] < 2 || sizes[i] >= (1ull << 31))
+            return set_err(ctx, QMC_EINVAL, "qmc_size_lattices: size %llu outside [2, 2^31)",
+                           (unsigned long long)sizes[i]);
+    const int ns = (int)plan->secs.size();
+    const int K = plan->sec_hi - plan->sec_lo + 1;
+    const int no = plan->eps_hi - plan->eps_lo + 1;
+    std::vector<qmc_coeff> coeff(no);
+    std::vector<double> ss((size_t)ns * m * K * 2);
+    qmc_result res{};
+    res.coeff = coeff.data();
+    res.sector_sums = ss.data();
+    int rc = qmc_integrate(ctx, plan, kin, 1, pilot, nullptr, shifts, m, &res);
+    if (rc) return rc;
+    // kernel class of every sector at this point: deformed sectors cost more
+    std::vector<double> coef(plan->n_terms), dcoef(plan->dexp.size()), w(ns);
+    qmc_contract(plan, kin, coef.data(), dcoef.data());
+    const double inv_n = 1.0 / (double)pilot->n;
+    double wsum = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        double spread = 0.0;
+        for (int q = 0; q < K; ++q)
+            for (int c = 0; c < 2; ++c) {
+                double mean = 0.0;
+                for (int k = 0; k < m; ++k) mean += ss[(((size_t)s * m + k) * K + q) * 2 + c];
+                mean /= m;
+                for (int k = 0; k < m; ++k)
+                    spread = std::max(spread, std::fabs(ss[(((size_t)s * m + k) * K + q) * 2 + c] -
+                                                        mean) * inv_n);
+            }
+        double lam = 0.0;
+        const int dm = qmc_sector_mode(plan, s, coef.data(), &lam);
+        const double cost = dm ? plan->secs[s].flops_deform : plan->secs[s].flops;
+        spread = std::max(spread, 1e-300);
+        w[s] = std::cbrt(spread * spread / cost);
+        wsum += w[s];
+    }
+    for (int s = 0; s < ns; ++s) {
+        const double want = std::max(w[s] / wsum * (double)total_points, 1.0);
+        int best = 0;
+        for (int i = 1; i < n_sizes; ++i)
+            if (std::fabs(std::log((double)sizes[i]) - std::log(want)) <
+                std::fabs(std::log((double)sizes[best]) - std::log(want)))
+                best = i;
+        out_n[s] = sizes[best];
+    }
+    return QMC_OK;
+}
+
 extern "C" int qmc_job_set_graph(qmc_job *job, int enable)
 {
     if (!job) return QMC_EINVAL;
@@ -1156,6 +1212,8 @@ extern "C" int qmc_job_class_stats(const qmc_job *job, qmc_class_stat *out, int3
         st.evals = c.evals;
         st.algo_flops = c.flops;
         st.ms = (size_t)i < job->cls_ms.size() ? job->cls_ms[i] : -1.0;
+        st.variant = c.variant;
+        st.pad = 0;
     }
     *n = nc;
     return QMC_OK;
@@ -1182,6 +1240,7 @@ extern "C" int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *ki
     if (!ctx || !plan) return QMC_EINVAL;
     static const int ppls[] = {4, 16, 64, 256, 1024};
     static const int grids[] = {0, 4, 8};
+    static const int variants[] = {0, 1};
     std::map<std::string, std::pair<qmc_tune, std::pair<int, int>>> best;
     for (int ppl : ppls) {
         qmc_job *job = nullptr;
@@ -1191,8 +1250,12 @@ extern "C" int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *ki
         uint64_t nmax = 0;
         for (uint64_t v : job->n_per_sector) nmax = std::max(nmax, v);
         bool warmed = false;
+        for (int var : variants)
         for (int gpc : grids) {
-            for (qmc_class &c : job->classes) c.grid = gpc * ctx->n_cu;
+            for (qmc_class &c : job->classes) {
+                c.grid = gpc * ctx->n_cu;
+                c.variant = var;
+            }
             for (int rep = warmed ? 0 : -1; rep < 1; ++rep) {
                 rc = qmc_run(job);
                 if (!rc) {
@@ -1216,6 +1279,7 @@ extern "C" int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *ki
                     qmc_tune t;
                     t.ppl = ppl;
                     t.grid_per_cu = gpc;
+                    t.variant = var;
                     t.ms = ms;
                     best[key] = {t, {c.ks, c.dm}};
                 }
@@ -1235,6 +1299,8 @@ extern "C" int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *ki
                 ch.width = kv.second.second.second;
                 ch.points_per_lane = kv.second.first.ppl;
                 ch.grid_per_cu = kv.second.first.grid_per_cu;
+                ch.occupancy_variant = kv.second.first.variant;
+                ch.pad = 0;
                 ch.ms = kv.second.first.ms;
             }
             ++k;

@@ -21,6 +21,7 @@ struct qmc_serve_state;
 struct qmc_tune {
     int ppl = 0;                     // points per lane per work item
     int grid_per_cu = 0;             // persistent work-groups per CU (0: one per item)
+    int variant = 0;                 // occupancy build of the kernel class
     double ms = 0.0;                 // measured time of the class
 };
 
@@ -96,6 +97,7 @@ struct qmc_class {                   // items launched by one kernel instance
     int begin = 0, end = 0;
     int grid = 0;                    // work-groups (0: one per item)
     int ppl = 0;                     // lattice points per lane per item
+    int variant = 0;                 // occupancy build (0 swept default, 1 fewer waves)
     uint64_t evals = 0;              // integrand evaluations of one launch
     double flops = 0.0;              // algorithmic flops of one launch
 };

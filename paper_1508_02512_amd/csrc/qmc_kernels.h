@@ -7,15 +7,16 @@
 
 // Real (Euclidean) integrand for sectors with `ks` poles carrying ks + kb
 // Laurent orders, evaluated in FP64 or FP32; one work-group per item in
-// [item_begin, item_end).
-hipError_t qmc_launch_real(int ks, int kb, bool fp32, const qmc_launch_args &args, int grid,
-                           hipStream_t stream);
+// [item_begin, item_end).  variant 0 is the build with the swept occupancy,
+// variant 1 the build with one wave per SIMD fewer (less spilling).
+hipError_t qmc_launch_real(int ks, int kb, bool fp32, int variant, const qmc_launch_args &args,
+                           int grid, hipStream_t stream);
 
 // Complex integrand with contour deformation (Eq. 14) for sectors of
 // dimension <= dm (dm = qmc_cplx_dm(dim)); polynomial work in FP32 when
-// fp32, else FP64.
-hipError_t qmc_launch_cplx(int dm, int ks, int kb, bool fp32, const qmc_launch_args &args,
-                           int grid, hipStream_t stream);
+// fp32, else FP64; variant 0 built for four waves per SIMD, variant 1 for two.
+hipError_t qmc_launch_cplx(int dm, int ks, int kb, bool fp32, int variant,
+                           const qmc_launch_args &args, int grid, hipStream_t stream);
 int qmc_cplx_dm(int dim);
 bool qmc_cplx_supported(int dim, int ks, int kb);
 

@@ -9,17 +9,24 @@
 
 using namespace qmc;
 
-hipError_t qmc_launch_real_lo(int ks, int kb, const qmc_launch_args &args, int grid,
-                              hipStream_t stream);
-hipError_t qmc_launch_real_hi(int ks, int kb, const qmc_launch_args &args, int grid,
-                              hipStream_t stream);
-hipError_t qmc_launch_real_f32(int ks, int kb, const qmc_launch_args &args, int grid,
-                               hipStream_t stream);
+#define QMC_REAL_LAUNCHER(name)                                                      \
+    hipError_t name(int ks, int kb, const qmc_launch_args &args, int grid, hipStream_t stream);
+QMC_REAL_LAUNCHER(qmc_launch_real_lo)
+QMC_REAL_LAUNCHER(qmc_launch_real_hi)
+QMC_REAL_LAUNCHER(qmc_launch_real_f32)
+QMC_REAL_LAUNCHER(qmc_launch_real_lo_v1)
+QMC_REAL_LAUNCHER(qmc_launch_real_hi_v1)
+QMC_REAL_LAUNCHER(qmc_launch_real_f32_v1)
 
-hipError_t qmc_launch_real(int ks, int kb, bool fp32, const qmc_launch_args &args, int grid,
-                           hipStream_t stream)
+hipError_t qmc_launch_real(int ks, int kb, bool fp32, int variant, const qmc_launch_args &args,
+                           int grid, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
+    if (variant == 1) {
+        if (fp32) return qmc_launch_real_f32_v1(ks, kb, args, grid, stream);
+        return ks <= 2 ? qmc_launch_real_lo_v1(ks, kb, args, grid, stream)
+                       : qmc_launch_real_hi_v1(ks, kb, args, grid, stream);
+    }
     if (fp32) return qmc_launch_real_f32(ks, kb, args, grid, stream);
     return ks <= 2 ? qmc_launch_real_lo(ks, kb, args, grid, stream)
                    : qmc_launch_real_hi(ks, kb, args, grid, stream);

@@ -1,18 +1,20 @@
 // Dispatch of the deformed (complex) integrand kernels by kernel width.
 #include "qmc_kernels.h"
 
-hipError_t qmc_launch_cplx2(int ks, int kb, const qmc_launch_args &args, int grid,
-                            hipStream_t stream);
-hipError_t qmc_launch_cplx4(int ks, int kb, const qmc_launch_args &args, int grid,
-                            hipStream_t stream);
-hipError_t qmc_launch_cplx6(int ks, int kb, const qmc_launch_args &args, int grid,
-                            hipStream_t stream);
-hipError_t qmc_launch_cplx2_f32(int ks, int kb, const qmc_launch_args &args, int grid,
-                                hipStream_t stream);
-hipError_t qmc_launch_cplx4_f32(int ks, int kb, const qmc_launch_args &args, int grid,
-                                hipStream_t stream);
-hipError_t qmc_launch_cplx6_f32(int ks, int kb, const qmc_launch_args &args, int grid,
-                                hipStream_t stream);
+#define QMC_CPLX_LAUNCHER(name)                                                      \
+    hipError_t name(int ks, int kb, const qmc_launch_args &args, int grid, hipStream_t stream);
+QMC_CPLX_LAUNCHER(qmc_launch_cplx2)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx4)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx6)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx2_f32)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx4_f32)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx6_f32)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx2_v1)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx4_v1)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx6_v1)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx2_f32_v1)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx4_f32_v1)
+QMC_CPLX_LAUNCHER(qmc_launch_cplx6_f32_v1)
 
 int qmc_cplx_dm(int dim) { return dim <= 2 ? 2 : dim <= 4 ? 4 : dim <= 6 ? 6 : 0; }
 
@@ -27,15 +29,17 @@ bool qmc_cplx_supported(int dim, int ks, int kb)
     return dm != 0 && ks >= 0 && ks <= 2 && kb >= 1 && kb <= (dm == 2 ? 3 : 2);
 }
 
-hipError_t qmc_launch_cplx(int dm, int ks, int kb, bool fp32, const qmc_launch_args &args,
-                           int grid, hipStream_t stream)
+hipError_t qmc_launch_cplx(int dm, int ks, int kb, bool fp32, int variant,
+                           const qmc_launch_args &args, int grid, hipStream_t stream)
 {
+    typedef hipError_t (*launcher)(int, int, const qmc_launch_args &, int, hipStream_t);
+    // [variant][fp32][width 2, 4, 6]
+    static const launcher table[2][2][3] = {
+        {{qmc_launch_cplx2, qmc_launch_cplx4, qmc_launch_cplx6},
+         {qmc_launch_cplx2_f32, qmc_launch_cplx4_f32, qmc_launch_cplx6_f32}},
+        {{qmc_launch_cplx2_v1, qmc_launch_cplx4_v1, qmc_launch_cplx6_v1},
+         {qmc_launch_cplx2_f32_v1, qmc_launch_cplx4_f32_v1, qmc_launch_cplx6_f32_v1}}};
     if (grid <= 0) return hipSuccess;
-    if (dm == 2) return fp32 ? qmc_launch_cplx2_f32(ks, kb, args, grid, stream)
-                             : qmc_launch_cplx2(ks, kb, args, grid, stream);
-    if (dm == 4) return fp32 ? qmc_launch_cplx4_f32(ks, kb, args, grid, stream)
-                             : qmc_launch_cplx4(ks, kb, args, grid, stream);
-    if (dm == 6) return fp32 ? qmc_launch_cplx6_f32(ks, kb, args, grid, stream)
-                             : qmc_launch_cplx6(ks, kb, args, grid, stream);
-    return hipErrorInvalidValue;
+    if (variant < 0 || variant > 1 || (dm != 2 && dm != 4 && dm != 6)) return hipErrorInvalidValue;
+    return table[variant][fp32 ? 1 : 0][dm / 2 - 1](ks, kb, args, grid, stream);
 }

@@ -4,9 +4,9 @@
 hipError_t qmc_launch_cplx2(int ks, int kb, const qmc_launch_args &args, int grid,
                              hipStream_t stream)
 {
-    QMC_CPLX_CASE(2, 0, 1, double) QMC_CPLX_CASE(2, 0, 2, double)
-    QMC_CPLX_CASE(2, 1, 1, double) QMC_CPLX_CASE(2, 1, 2, double)
-    QMC_CPLX_CASE(2, 2, 1, double) QMC_CPLX_CASE(2, 2, 2, double)
-    QMC_CPLX_CASE(2, 0, 3, double) QMC_CPLX_CASE(2, 1, 3, double) QMC_CPLX_CASE(2, 2, 3, double)
+    QMC_CPLX_CASE(2, 0, 1, double, 0) QMC_CPLX_CASE(2, 0, 2, double, 0)
+    QMC_CPLX_CASE(2, 1, 1, double, 0) QMC_CPLX_CASE(2, 1, 2, double, 0)
+    QMC_CPLX_CASE(2, 2, 1, double, 0) QMC_CPLX_CASE(2, 2, 2, double, 0)
+    QMC_CPLX_CASE(2, 0, 3, double, 0) QMC_CPLX_CASE(2, 1, 3, double, 0) QMC_CPLX_CASE(2, 2, 3, double, 0)
     return hipErrorInvalidValue;
 }

@@ -4,9 +4,9 @@
 hipError_t qmc_launch_cplx2_f32(int ks, int kb, const qmc_launch_args &args, int grid,
                                  hipStream_t stream)
 {
-    QMC_CPLX_CASE(2, 0, 1, float) QMC_CPLX_CASE(2, 0, 2, float)
-    QMC_CPLX_CASE(2, 1, 1, float) QMC_CPLX_CASE(2, 1, 2, float)
-    QMC_CPLX_CASE(2, 2, 1, float) QMC_CPLX_CASE(2, 2, 2, float)
-    QMC_CPLX_CASE(2, 0, 3, float) QMC_CPLX_CASE(2, 1, 3, float) QMC_CPLX_CASE(2, 2, 3, float)
+    QMC_CPLX_CASE(2, 0, 1, float, 0) QMC_CPLX_CASE(2, 0, 2, float, 0)
+    QMC_CPLX_CASE(2, 1, 1, float, 0) QMC_CPLX_CASE(2, 1, 2, float, 0)
+    QMC_CPLX_CASE(2, 2, 1, float, 0) QMC_CPLX_CASE(2, 2, 2, float, 0)
+    QMC_CPLX_CASE(2, 0, 3, float, 0) QMC_CPLX_CASE(2, 1, 3, float, 0) QMC_CPLX_CASE(2, 2, 3, float, 0)
     return hipErrorInvalidValue;
 }

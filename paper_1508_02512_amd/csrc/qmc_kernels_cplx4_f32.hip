@@ -4,8 +4,8 @@
 hipError_t qmc_launch_cplx4_f32(int ks, int kb, const qmc_launch_args &args, int grid,
                                  hipStream_t stream)
 {
-    QMC_CPLX_CASE(4, 0, 1, float) QMC_CPLX_CASE(4, 0, 2, float)
-    QMC_CPLX_CASE(4, 1, 1, float) QMC_CPLX_CASE(4, 1, 2, float)
-    QMC_CPLX_CASE(4, 2, 1, float) QMC_CPLX_CASE(4, 2, 2, float)
+    QMC_CPLX_CASE(4, 0, 1, float, 0) QMC_CPLX_CASE(4, 0, 2, float, 0)
+    QMC_CPLX_CASE(4, 1, 1, float, 0) QMC_CPLX_CASE(4, 1, 2, float, 0)
+    QMC_CPLX_CASE(4, 2, 1, float, 0) QMC_CPLX_CASE(4, 2, 2, float, 0)
     return hipErrorInvalidValue;
 }

@@ -4,8 +4,8 @@
 hipError_t qmc_launch_cplx6(int ks, int kb, const qmc_launch_args &args, int grid,
                              hipStream_t stream)
 {
-    QMC_CPLX_CASE(6, 0, 1, double) QMC_CPLX_CASE(6, 0, 2, double)
-    QMC_CPLX_CASE(6, 1, 1, double) QMC_CPLX_CASE(6, 1, 2, double)
-    QMC_CPLX_CASE(6, 2, 1, double) QMC_CPLX_CASE(6, 2, 2, double)
+    QMC_CPLX_CASE(6, 0, 1, double, 0) QMC_CPLX_CASE(6, 0, 2, double, 0)
+    QMC_CPLX_CASE(6, 1, 1, double, 0) QMC_CPLX_CASE(6, 1, 2, double, 0)
+    QMC_CPLX_CASE(6, 2, 1, double, 0) QMC_CPLX_CASE(6, 2, 2, double, 0)
     return hipErrorInvalidValue;
 }

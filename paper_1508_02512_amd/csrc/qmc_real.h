@@ -503,16 +503,19 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
 //            scratch per launch) / 6 (45.7 vs 58.7)
 //   poles 3: 3 (99.2; 2 gives 116.6, 4 gives 106.4) / 4 (73.3 vs 88.6)
 //   poles 4: 2 (103.1; 1 gives 161.6, 3 gives 115.1) / 3 (82.2 vs 103.0)
-template <int KS, typename T>
+template <int KS, typename T, int V>
 constexpr int min_waves()
 {
-    if (sizeof(T) == 8) return KS <= 2 ? 4 : (KS == 3 ? 3 : 2);
-    return KS <= 1 ? 1 : (KS == 2 ? 6 : (KS == 3 ? 4 : 3));
+    constexpr int base = sizeof(T) == 8 ? (KS <= 2 ? 4 : (KS == 3 ? 3 : 2))
+                                        : (KS <= 1 ? 1 : (KS == 2 ? 6 : (KS == 3 ? 4 : 3)));
+    // occupancy variant 1: one wave fewer than the swept default, trading
+    // latency hiding for fewer spills (the autotuner chooses per workload)
+    return V == 0 ? base : (base > 1 ? base - 1 : 1);
 }
 
-template <int KS, int K, typename T>
+template <int KS, int K, typename T, int V>
 __global__ __launch_bounds__(QMC_BLOCK)
-__attribute__((amdgpu_waves_per_eu(min_waves<KS, T>(), 8))) void qmc_eval_real(qmc_launch_args A)
+__attribute__((amdgpu_waves_per_eu(min_waves<KS, T, V>(), 8))) void qmc_eval_real(qmc_launch_args A)
 {
     // per-lane power table: slot s of lane x at pw[s * QMC_BLOCK + x]; the
     // last slot is the constant 1 that pads the term programs
@@ -527,16 +530,18 @@ __attribute__((amdgpu_waves_per_eu(min_waves<KS, T>(), 8))) void qmc_eval_real(q
 
 } // namespace qmc_real
 
-#define QMC_REAL_CASE(KS, KB, T)                                                    \
+#define QMC_REAL_CASE(KS, KB, T, V)                                                 \
     if (ks == KS && kb == KB) {                                                     \
-        hipLaunchKernelGGL((qmc_real::qmc_eval_real<KS, KS + KB, T>), dim3(grid),    \
+        hipLaunchKernelGGL((qmc_real::qmc_eval_real<KS, KS + KB, T, V>), dim3(grid), \
                            dim3(QMC_BLOCK), 0, stream, args);                       \
         return hipGetLastError();                                                   \
     }
 
-#define QMC_REAL_CASES(T)                                                           \
-    QMC_REAL_CASE(0, 1, T) QMC_REAL_CASE(0, 2, T) QMC_REAL_CASE(0, 3, T)           \
-    QMC_REAL_CASE(1, 1, T) QMC_REAL_CASE(1, 2, T) QMC_REAL_CASE(1, 3, T)           \
-    QMC_REAL_CASE(2, 1, T) QMC_REAL_CASE(2, 2, T) QMC_REAL_CASE(2, 3, T)           \
-    QMC_REAL_CASE(3, 1, T) QMC_REAL_CASE(3, 2, T) QMC_REAL_CASE(3, 3, T)           \
-    QMC_REAL_CASE(4, 1, T) QMC_REAL_CASE(4, 2, T) QMC_REAL_CASE(4, 3, T)
+#define QMC_REAL_CASES_LO(T, V)                                                     \
+    QMC_REAL_CASE(0, 1, T, V) QMC_REAL_CASE(0, 2, T, V) QMC_REAL_CASE(0, 3, T, V)  \
+    QMC_REAL_CASE(1, 1, T, V) QMC_REAL_CASE(1, 2, T, V) QMC_REAL_CASE(1, 3, T, V)  \
+    QMC_REAL_CASE(2, 1, T, V) QMC_REAL_CASE(2, 2, T, V) QMC_REAL_CASE(2, 3, T, V)
+
+#define QMC_REAL_CASES_HI(T, V)                                                     \
+    QMC_REAL_CASE(3, 1, T, V) QMC_REAL_CASE(3, 2, T, V) QMC_REAL_CASE(3, 3, T, V)  \
+    QMC_REAL_CASE(4, 1, T, V) QMC_REAL_CASE(4, 2, T, V) QMC_REAL_CASE(4, 3, T, V)

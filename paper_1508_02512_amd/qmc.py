@@ -75,13 +75,15 @@ class qmc_result(C.Structure):
 
 class qmc_tune_choice(C.Structure):
     _fields_ = [("poles", C.c_int32), ("width", C.c_int32), ("points_per_lane", C.c_int32),
-                ("grid_per_cu", C.c_int32), ("ms", C.c_double)]
+                ("grid_per_cu", C.c_int32), ("occupancy_variant", C.c_int32),
+                ("pad", C.c_int32), ("ms", C.c_double)]
 
 
 class qmc_class_stat(C.Structure):
     _fields_ = [("poles", C.c_int32), ("width", C.c_int32), ("points_per_lane", C.c_int32),
                 ("grid", C.c_int32), ("items", C.c_int32), ("precision", C.c_int32),
-                ("evals", C.c_uint64), ("algo_flops", C.c_double), ("ms", C.c_double)]
+                ("evals", C.c_uint64), ("algo_flops", C.c_double), ("ms", C.c_double),
+                ("variant", C.c_int32), ("pad", C.c_int32)]
 
 
 class qmc_request(C.Structure):
@@ -102,6 +104,9 @@ _SIGS = {
     "qmc_integrate": (C.c_int, [C.c_void_p, C.c_void_p, P(C.c_double), C.c_int32,
                                 P(qmc_lattice), P(qmc_lattice), P(C.c_double), C.c_int32,
                                 P(qmc_result)]),
+    "qmc_size_lattices": (C.c_int, [C.c_void_p, C.c_void_p, P(C.c_double), P(qmc_lattice),
+                                    P(C.c_double), C.c_int32, C.c_uint64, P(C.c_uint64),
+                                    C.c_int32, P(C.c_uint64)]),
     "qmc_integrate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, P(C.c_double), C.c_int32,
                                         P(qmc_lattice), P(qmc_lattice), P(C.c_double),
                                         C.c_int32, P(qmc_result)]),
@@ -334,7 +339,8 @@ class Plan:
                                           C.byref(lat) if lat is not None else None, lps,
                                           _dptr(shifts), shifts.shape[0], ch, 64, C.byref(n)))
         return [{"poles": c.poles, "width": c.width, "points_per_lane": c.points_per_lane,
-                 "grid_per_cu": c.grid_per_cu, "ms": c.ms} for c in ch[:min(n.value, 64)]]
+                 "grid_per_cu": c.grid_per_cu, "occupancy_variant": c.occupancy_variant,
+                 "ms": c.ms} for c in ch[:min(n.value, 64)]]
 
 
 class Request:
@@ -438,25 +444,17 @@ class Job:
             pass
 
 
-def size_lattices(plan, kin, total_points, primes, pilot_n, pilot_z, shifts, cost=None):
-    """Per-sector lattice sizes for a fixed total budget of lattice points.
-
-    A pilot run at n = pilot_n gives each sector's spread c_s over the shifts
-    (largest over Laurent orders).  With a QMC error ~ c_s / n_s and a cost
-    ~ cost_s n_s, minimising the summed variance sum_s (c_s / n_s)^2 for the
-    budget gives n_s proportional to (c_s^2 / cost_s)^(1/3); sizes are then
-    rounded (in log scale) to the nearest available prime."""
-    pilot = plan.integrate(kin, (pilot_n, pilot_z), shifts, sector_sums=True)
-    ss = pilot["sector_sums"][0] / float(pilot_n)          # [sectors][m][orders]
-    spread = np.abs(ss - ss.mean(axis=1, keepdims=True)).max(axis=(1, 2))
-    spread = np.maximum(spread, 1e-30)
-    cost = np.ones_like(spread) if cost is None else np.asarray(cost, dtype=float)
-    w = np.cbrt(spread ** 2 / cost)
-    share = w / w.sum()
-    want = share * float(total_points)
-    primes = np.asarray(sorted(primes))
-    out = []
-    for v in want:
-        i = int(np.argmin(np.abs(np.log(primes) - np.log(max(v, primes[0])))))
-        out.append(int(primes[i]))
-    return out
+def size_lattices(plan, kin, total_points, sizes, pilot_n, pilot_z, shifts):
+    """Per-sector lattice sizes for a total budget of lattice points: the
+    library's variance-weighted sizing (qmc_size_lattices) from a pilot run
+    at n = pilot_n; every size is one of `sizes`."""
+    kin = np.ascontiguousarray(np.atleast_2d(kin)[0], dtype=np.float64)
+    shifts = np.ascontiguousarray(shifts, dtype=np.float64)
+    avail = np.ascontiguousarray(sorted(sizes), dtype=np.uint64)
+    out = np.zeros(plan.n_sectors, dtype=np.uint64)
+    pilot = plan._lattice(pilot_n, pilot_z)
+    plan.ctx.check(lib().qmc_size_lattices(
+        plan.ctx.h, plan.h, _dptr(kin), C.byref(pilot), _dptr(shifts), shifts.shape[0],
+        int(total_points), avail.ctypes.data_as(P(C.c_uint64)), len(avail),
+        out.ctypes.data_as(P(C.c_uint64))))
+    return [int(v) for v in out]

@@ -73,6 +73,7 @@ def test_autotune_then_same_result():
     before = plan.integrate(kin, None, sh, lat_per_sector=lats, sector_sums=True)
     choices = plan.autotune(kin, None, sh, lat_per_sector=lats)
     assert choices and all(c["points_per_lane"] > 0 for c in choices)
+    assert all(c["occupancy_variant"] in (0, 1) for c in choices)
     after = plan.integrate(kin, None, sh, lat_per_sector=lats, sector_sums=True)
     b, a = before["sector_sums"], after["sector_sums"]
     assert np.allclose(a, b, rtol=1e-12, atol=1e-13 * np.max(np.abs(b)))
@@ -131,3 +132,27 @@ def test_more_items_than_one_launch_can_hold():
     a, b = out
     assert np.allclose(a["mean"], b["mean"], rtol=1e-12, atol=0)
     assert np.allclose(a["err_re"], b["err_re"], rtol=1e-9, atol=0)
+
+
+def test_size_lattices_in_the_library():
+    """qmc_size_lattices: every sector gets one of the offered sizes, their
+    sum is the budget up to the log-scale rounding, and the sector with the
+    largest pilot spread over the shifts gets at least the size of the one
+    with the smallest."""
+    print("batch: variance-weighted lattice sizes", flush=True)
+    plan, info = gpu_plan("np_vertex", lam=0.5)
+    kin = fe.kin_vector(info, {"s": 4.5, "msq": 1.0})
+    avail = [10007, 65521, 100003, 262139, 1000003, 4194301, 10000019]
+    total = 10 ** 6 * plan.n_sectors
+    sizes = qmc.size_lattices(plan, kin, total, avail, 65521, lattice(65521),
+                              shift_table(1, 8, 8))
+    assert len(sizes) == plan.n_sectors and set(sizes) <= set(avail)
+    assert total / 4 <= sum(sizes) <= total * 4
+    pilot = plan.integrate(kin, (65521, lattice(65521)), shift_table(1, 8, 8),
+                           sector_sums=True)
+    ss = pilot["sector_sums"][0] / 65521.0
+    spread = np.abs(ss - ss.mean(axis=1, keepdims=True)).max(axis=(1, 2))
+    assert sizes[int(np.argmax(spread))] >= sizes[int(np.argmin(spread))]
+    with pytest.raises(qmc.QMCError):
+        qmc.size_lattices(plan, kin, total, [1], 65521, lattice(65521), shift_table(1, 8, 8))
+    plan.close()
