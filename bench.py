@@ -253,7 +253,8 @@ def serve_bench(qmc, fe, PROBLEMS, lattice, n_req, rate, fp32, slots, log,
         secs, info = fe.decompose(PROBLEMS[name], strategy)
         plans[name] = (ctx.plan(fe.sector_arrays(secs, info), info, 0,
                                 fe.prefactor_series(info, 12), lam=lam, precision=prec), info)
-    z = lattice(1 << 24)
+    from seeded_inputs.lattice import embedded_lattice
+    z = embedded_lattice()
     gaps = rng.exponential(1.0 / rate, size=n_req)
     kinds = rng.integers(0, 3, size=n_req)
     reqs = []

@@ -216,7 +216,49 @@ def lattice(n: int, kind: str = "korobov") -> np.ndarray:
 
 
 def stored_sizes() -> list[int]:
-    return sorted(int(k) for k in _table())
+    return sorted(int(k) for k in _table() if k.isdigit())
+
+
+# The embedded (extensible) rank-1 rule of the serving path: one odd
+# generating vector z, used at every n = 2^k as z mod 2^k, so that the
+# points of size 2^k are the even-index points of size 2^(k+1) (Section
+# III's lattice rule grown by doubling).  It is chosen among seeded Korobov
+# candidates a (z = (1, a, a^2, ...) mod 2^24) by the P_2 criterion summed
+# over the sizes the serving path uses, n = 2^14 .. 2^22, instead of at a
+# single n.
+EMBED_KMIN, EMBED_KMAX = 14, 22
+EMBED_N = 1 << 24
+
+
+def embedded_criterion(a: int, kmin: int = EMBED_KMIN, kmax: int = EMBED_KMAX,
+                       dim: int = SEARCH_DIM) -> float:
+    """Sum over n = 2^kmin .. 2^kmax of P_2 of the rule (z mod n, n) with
+    z = (1, a, a^2, ...) mod 2^24."""
+    z = korobov_vector(EMBED_N, a, dim)
+    return sum(p2_criterion(1 << k, [v % (1 << k) for v in z]) for k in range(kmin, kmax + 1))
+
+
+def _embedded_one(a: int) -> tuple[int, float]:
+    return a, embedded_criterion(a)
+
+
+def search_embedded(count: int = 64) -> dict:
+    from multiprocessing import Pool
+    cands = korobov_candidates(EMBED_N, count)
+    with Pool(min(8, os.cpu_count() or 1)) as pool:
+        scores = dict(pool.map(_embedded_one, cands))
+    a = min(cands, key=lambda c: scores[c])
+    return {"a": a, "z": korobov_vector(EMBED_N, a, DMAX), "criterion": scores[a],
+            "kmin": EMBED_KMIN, "kmax": EMBED_KMAX, "candidates": count,
+            "search_dim": SEARCH_DIM}
+
+
+def embedded_lattice() -> np.ndarray:
+    """The stored odd generating vector z[DMAX] of the embedded rule for
+    n = 2^k (serving); reduce it mod n for a rule of size n."""
+    z = np.array(_table()["embedded"]["z"], dtype=np.uint32)
+    assert z.shape == (DMAX,) and np.all(z % 2 == 1)
+    return z
 
 
 def _candidate_count(n: int) -> int:
@@ -252,15 +294,24 @@ def main() -> None:
         for n, rec in pool.imap_unordered(_make_one, todo):
             old[str(n)] = rec
             print(n, rec["a"], rec["p2"], flush=True)
-            with open(_DATA, "w") as fh:
-                json.dump({k: old[k] for k in sorted(old, key=int)}, fh, indent=1)
+            _dump(old)
     todo = [n for n in PRIME_SIZES if n <= CBC_MAX_N and "cbc" not in old[str(n)]]
     with Pool(min(4, os.cpu_count() or 1)) as pool:
         for n, rec in pool.imap_unordered(_make_cbc, todo):
             old[str(n)]["cbc"] = rec
             print(n, "cbc", rec["p2"], flush=True)
-            with open(_DATA, "w") as fh:
-                json.dump({k: old[k] for k in sorted(old, key=int)}, fh, indent=1)
+            _dump(old)
+    if "embedded" not in old:
+        old["embedded"] = search_embedded()
+        print("embedded", old["embedded"]["a"], old["embedded"]["criterion"], flush=True)
+        _dump(old)
+
+
+def _dump(table: dict) -> None:
+    keys = sorted((k for k in table if k.isdigit()), key=int) + \
+        sorted(k for k in table if not k.isdigit())
+    with open(_DATA, "w") as fh:
+        json.dump({k: table[k] for k in keys}, fh, indent=1)
 
 
 if __name__ == "__main__":

@@ -54,14 +54,14 @@ def sample_sectors(name, per_class=8, kin=None, strategy="iterated"):
 
 def compare_sectors(name, kin, n, m, eps_hi=0, lam=0.0, r=2, ppl=0, tol=1e-12,
                     sectors=None, seed=0, quad_from=2, precision=qmc.QMC_FP64,
-                    strategy="iterated"):
+                    strategy="iterated", kind="korobov"):
     """Max over (sector, shift, order) of |gpu - oracle| / sum|terms|.
 
     Sectors with at least `quad_from` poles are compared with the oracle's
     binary128 build: the mixed differences of Eq. 11 amplify the FP64
     oracle's own rounding beyond the parity bar there."""
     plan, info = gpu_plan(name, eps_hi, lam, r, ppl, precision, strategy)
-    z = lattice(n)
+    z = lattice(n, kind)
     shifts = shift_table(seed, m, 8)
     res = plan.integrate(fe.kin_vector(info, kin), (n, z), shifts, sector_sums=True)
     osecs, oinfo = oracle_sectors(name, strategy)

@@ -115,12 +115,12 @@ def test_fp32_serving_target_floor():
     """FP32-eval plans carry a rounding bias (measured up to 2.7e-6 relative
     on the double box); serving requests asking for less than 1e-5 on such
     a plan are refused."""
-    from seeded_inputs.lattice import lattice as lat
+    from seeded_inputs.lattice import embedded_lattice
     plan, info = gpu_plan("box", precision=FP32)
     kin = fe.kin_vector(info, {"s": -3.0, "t": -2.0})
     with pytest.raises(qmc.QMCError) as e:
-        qmc.submit(plan, kin, 1e-6, 1 << 10, 1 << 16, 4, 1, lat(1 << 24))
+        qmc.submit(plan, kin, 1e-6, 1 << 10, 1 << 16, 4, 1, embedded_lattice())
     assert e.value.code == -1
-    r = qmc.submit(plan, kin, 1e-5, 1 << 10, 1 << 16, 4, 1, lat(1 << 24)).wait(60)
+    r = qmc.submit(plan, kin, 1e-5, 1 << 10, 1 << 16, 4, 1, embedded_lattice()).wait(60)
     assert r["rc"] in (0, -7)
     plan.close()

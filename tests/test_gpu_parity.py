@@ -49,6 +49,18 @@ def test_finite_triangle_no_poles():
                     65521, 3)
 
 
+@pytest.mark.parametrize("name,kin,n", [
+    ("box", {"s": -3.0, "t": -2.0}, 10007),
+    ("doublebox", {"s": -3.0, "t": -1.0}, 4099),
+])
+def test_cbc_generating_vectors(name, kin, n):
+    """Lattices with the stored fast-CBC generating vectors (instead of
+    Korobov ones): per-sector parity against the oracle on the same vector."""
+    print(f"{name} n={n} CBC vector", flush=True)
+    compare_sectors(name, kin, n, 3, kind="cbc",
+                    sectors=None if name == "box" else sample_sectors(name, per_class=4))
+
+
 @pytest.mark.parametrize("r", [0, 1, 3])
 def test_korobov_orders(r):
     print(f"box r={r}", flush=True)

@@ -6,12 +6,12 @@ import pytest
 from gpu_util import assert_assembly_matches, ctx, gpu_plan, oracle_assembled
 from paper_1508_02512_amd import frontend as fe
 from paper_1508_02512_amd import qmc
-from seeded_inputs.lattice import lattice
+from seeded_inputs.lattice import embedded_lattice
 from seeded_inputs.rng import shift_table
 
 pytestmark = pytest.mark.gpu
 
-Z = lattice(1 << 24)          # odd Korobov vector, used for every n = 2^k
+Z = embedded_lattice()        # odd vector of the embedded rule, used for every n = 2^k
 
 
 def _box_kin(info, s=-3.0, t=-2.0):
@@ -156,7 +156,7 @@ def test_lambda_backoff_recovers():
     assert plain["rc"] == -6 and plain["lambda_halvings"] == 0
     r = qmc.submit(plan, kin, 1e-3, 1 << 12, 1 << 20, 8, 3, Z, lambda_halvings=4).wait(120)
     assert r["rc"] == 0 and 1 <= r["lambda_halvings"] <= 4 and r["violations"] == 0
-    ref = qmc.submit(safe, kin, 1e-3, 1 << 12, 1 << 20, 8, 3, Z).wait(120)
+    ref = qmc.submit(safe, kin, 1e-3, 1 << 12, 1 << 23, 8, 3, Z).wait(120)
     assert ref["rc"] == 0
     err = np.hypot(r["err_re"], r["err_im"]) + np.hypot(ref["err_re"], ref["err_im"])
     assert np.all(np.abs(r["mean"] - ref["mean"]) <= 5 * err + 1e-12)

@@ -3,6 +3,7 @@
 import math
 
 import numpy as np
+import pytest
 
 from seeded_inputs import lattice as L
 from seeded_inputs.rng import shift_table, splitmix64
@@ -110,3 +111,20 @@ def test_stored_cbc_vectors():
             # over all 8 components CBC is at least as good as the Korobov pick
             k = [int(v) for v in lattice(n)]
             assert p2_criterion(n, z) <= p2_criterion(n, k) * 1.0000001
+
+
+def test_embedded_vector_for_the_doubling_rule():
+    """The stored embedded generating vector: odd in every component (so it
+    is coprime to every 2^k), z mod 2^k of one vector gives every size, its
+    summed P_2 over n = 2^14 .. 2^22 is the stored one, and it is no worse
+    than the Korobov vector searched at n = 2^24 alone (one of its
+    candidates)."""
+    from seeded_inputs import lattice as L
+    rec = L._table()["embedded"]
+    z = L.embedded_lattice()
+    assert np.all(z % 2 == 1)
+    assert list(z) == L.korobov_vector(L.EMBED_N, rec["a"], L.DMAX)
+    crit = L.embedded_criterion(rec["a"])
+    assert crit == pytest.approx(rec["criterion"], rel=1e-12)
+    plain = L.embedded_criterion(L._table()[str(1 << 24)]["a"])
+    assert crit <= plain
