@@ -8,28 +8,32 @@
 // positive, so shorter sequences suffice:
 //
 //   ln(x), x > 0:   x = m 2^e with m in [sqrt(1/2), sqrt(2)), f = m - 1,
-//                   s = f / (2 + f), ln(1 + f) = 2 atanh(s) written as
-//                   f - s (f - R(s^2)) with the atanh series
-//                   R(z) = sum_k 2 z^k / (2k + 1) (the argument reduction
-//                   and rearrangement of the classical fdlibm scheme; here
-//                   with the exact series coefficients, one more term than
-//                   needed for |s| <= 3 - 2 sqrt(2): truncation < 1e-18);
-//                   e ln 2 added with ln 2 split into a 33-bit head (exact
-//                   product) and a tail.
+//                   s = f / (2 + f), ln(1 + f) = 2 atanh(s) = 2 s + s R with
+//                   R = z Q(z), z = s^2, Q(z) = 2 (atanh(s) - s) / s^3 a
+//                   degree-6 Chebyshev fit, summed as f - (f^2/2 - s (f^2/2
+//                   + R)) (the argument reduction and rearrangement of the
+//                   classical fdlibm scheme); e ln 2 added with ln 2 split
+//                   into a 33-bit head (exact product) and a tail.
 //   exp(x):         Cody-Waite reduction x = k ln 2 + r, |r| <= ln(2) / 2,
-//                   Taylor polynomial of degree 13 (truncation < 5e-18),
-//                   scaled by 2^k with ldexp.
-//   log1p(x), x > -1: u = 1 + x rounded, ln(u) corrected by the rounding
-//                   error of u to first order, (x - (u - 1)) / u.
-//   expm1(x):       the same reduction, 2^k (e^r - 1) + (2^k - 1) with the
-//                   Taylor series of e^r - 1.
+//                   e^r = 1 + (r + r^2 P(r)) with P(r) = (e^r - 1 - r) / r^2
+//                   a degree-10 Chebyshev fit, scaled by 2^k with ldexp.
+//   log1p(x), x > -1: u = 1 + x rounded and its rounding error c; with
+//                   u = m 2^e reduced as for ln, ln(1 + x) = e ln 2 +
+//                   ln(1 + f') with f' = (m - 1) + c 2^-e, so the rounding
+//                   of u never reaches the result.
+//   expm1(x):       the same reduction, 2^k (e^r - 1) + (2^k - 1) with
+//                   e^r - 1 = r + r^2 P(r).
 //
-// Errors are a few units in the last place, checked against the host
-// library on wide samples by the tests.  The float overloads (FP32
-// evaluation mode) use the device library.
+// The fits come from gen_math_coeffs.py (qmc_math_coeffs.h), which checks
+// each rounded polynomial against its error budget.  Errors are a few
+// units in the last place, checked against the host library on wide
+// samples by the tests.  The float overloads (FP32 evaluation mode) use
+// the device library.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "qmc_math_coeffs.h"
 
 namespace qmc_math {
 
@@ -48,50 +52,67 @@ __device__ __forceinline__ double rcp(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// polynomial of degree N with coefficients c[0] (highest) .. c[N]
+template <int N>
+__device__ __forceinline__ double horner(const double (&c)[N + 1], double x)
+{
+    double p = c[0];
+#pragma unroll
+    for (int i = 1; i <= N; ++i) p = fma(p, x, c[i]);
+    return p;
+}
+
 // ln(1 + f) for f in [sqrt(1/2) - 1, sqrt(2) - 1)
 __device__ __forceinline__ double ln1pf_reduced(double f)
 {
     const double s = f * rcp(2.0 + f);
     const double z = s * s;
-    double R = 2.0 / 23.0;
-    R = fma(R, z, 2.0 / 21.0);
-    R = fma(R, z, 2.0 / 19.0);
-    R = fma(R, z, 2.0 / 17.0);
-    R = fma(R, z, 2.0 / 15.0);
-    R = fma(R, z, 2.0 / 13.0);
-    R = fma(R, z, 2.0 / 11.0);
-    R = fma(R, z, 2.0 / 9.0);
-    R = fma(R, z, 2.0 / 7.0);
-    R = fma(R, z, 2.0 / 5.0);
-    R = fma(R, z, 2.0 / 3.0);
-    R *= z;
+    const double R = z * horner<LN_Q_DEG>(LN_Q, z);
     // ln(1 + f) = 2s + s R = f - s f + s R;  with hfsq = f^2 / 2 the
     // equivalent f - (hfsq - s (hfsq + R)) keeps the rounding of s small
     const double hfsq = 0.5 * f * f;
     return f - (hfsq - s * (hfsq + R));
 }
 
-// natural logarithm of a positive finite x
-__device__ __forceinline__ double ln(double x)
+// u = m 2^e with m in [sqrt(1/2), sqrt(2)), u > 0 finite
+__device__ __forceinline__ void reduce_ln(double u, double &m, int &e)
 {
-    double m = __builtin_amdgcn_frexp_mant(x);        // [1/2, 1)
-    int e = __builtin_amdgcn_frexp_exp(x);
+    m = __builtin_amdgcn_frexp_mant(u);               // [1/2, 1)
+    e = __builtin_amdgcn_frexp_exp(u);
     const bool lo = m < SQRT_HALF;
     m = lo ? 2.0 * m : m;
     e = lo ? e - 1 : e;
+}
+
+// natural logarithm of a positive finite x
+__device__ __forceinline__ double ln(double x)
+{
+    double m;
+    int e;
+    reduce_ln(x, m, e);
     const double k = (double)e;
     const double l = ln1pf_reduced(m - 1.0);          // m - 1 is exact
     return fma(k, LN2_HI, fma(k, LN2_LO, l));
 }
 
-// ln(1 + x) for x > -1
+// ln(1 + x) for x > -1: the rounding error c of u = 1 + x is added to the
+// reduced argument, where it is scaled like u itself
 __device__ __forceinline__ double ln1p(double x)
 {
     const double u = 1.0 + x;
     const double c = x - (u - 1.0);                   // rounding error of u
-    // for |x| below ulp(1) the correction is the whole result, so the
-    // reciprocal must be accurate
-    return ln(u) + c * rcp(u);
+    double m;
+    int e;
+    reduce_ln(u, m, e);
+    const double f = (m - 1.0) + __builtin_amdgcn_ldexp(c, -e);
+    const double k = (double)e;
+    return fma(k, LN2_HI, fma(k, LN2_LO, ln1pf_reduced(f)));
+}
+
+// e^r - 1 for |r| <= ln(2) / 2
+__device__ __forceinline__ double expm1_reduced(double r)
+{
+    return fma(r * r, horner<EXPM1_P_DEG>(EXPM1_P, r), r);
 }
 
 // e^x for finite x (results below the normal range may flush towards 0)
@@ -101,50 +122,21 @@ __device__ __forceinline__ double ex(double x)
     const double k = __builtin_rint(x * LOG2E);
     double r = fma(-k, LN2_HI, x);
     r = fma(-k, LN2_LO, r);
-    double p = 1.0 / 6227020800.0;               // 1/13!
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    return __builtin_amdgcn_ldexp(p, (int)k);
+    return __builtin_amdgcn_ldexp(1.0 + expm1_reduced(r), (int)k);
 }
 
 // e^x - 1 for finite x: with x = k ln 2 + r as in ex(),
-// e^x - 1 = 2^k (e^r - 1) + (2^k - 1), e^r - 1 from its Taylor series of
-// degree 14 (truncation < 3e-19 relative for |r| <= ln(2) / 2); 2^k - 1 is
-// exact and the two terms never cancel by more than a factor of about 2.5.
-// k = 0 for |x| < ln(2) / 2, where the result is the series itself.
+// e^x - 1 = 2^k (e^r - 1) + (2^k - 1); 2^k - 1 is exact and the two terms
+// never cancel by more than a factor of about 2.5.  k = 0 for
+// |x| < ln(2) / 2, where the result is e^r - 1 itself.
 __device__ __forceinline__ double exm1(double x)
 {
     x = fmin(fmax(x, -80.0), 709.0);
     const double k = __builtin_rint(x * LOG2E);
     double r = fma(-k, LN2_HI, x);
     r = fma(-k, LN2_LO, r);
-    double p = 1.0 / 87178291200.0;              // 1/14!, then down to 1/2
-    p = fma(p, r, 1.0 / 6227020800.0);
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(r * r, p, r);                             // e^r - 1 = r + r^2 (1/2 + ...)
     const int ki = (int)k;
-    return __builtin_amdgcn_ldexp(p, ki) + (__builtin_amdgcn_ldexp(1.0, ki) - 1.0);
+    return __builtin_amdgcn_ldexp(expm1_reduced(r), ki) + (__builtin_amdgcn_ldexp(1.0, ki) - 1.0);
 }
 
 __device__ __forceinline__ float ln(float x) { return logf(x); }
