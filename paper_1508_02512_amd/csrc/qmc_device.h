@@ -30,6 +30,10 @@ struct qmc_sec_dev {
     int32_t aint[QMC_DMAX];  // a_j if a small non-negative integer, else QMC_NO_INT
     int32_t um[QMC_NMASK + 1];   // U terms of mask m: [um[m], um[m+1])
     int32_t fm[QMC_NMASK + 1];   // F terms of mask m: [fm[m], fm[m+1])
+    // within each mask: terms of at most four power-table factors first,
+    // then five to eight ([um1[m], um2[m])), then the exp form ([um2[m], um[m+1]))
+    int32_t um1[QMC_NMASK], um2[QMC_NMASK];
+    int32_t fm1[QMC_NMASK], fm2[QMC_NMASK];
     int32_t d1[QMC_DMAX + 1];    // dF/dt_j terms: [d1[j], d1[j+1]) in the derivative table
     int32_t d2[QMC_DMAX * (QMC_DMAX + 1) / 2 + 1];  // d2F/dt_j dt_k, j <= k, row-major
     double u0, u1, f0, f1;
@@ -65,6 +69,7 @@ struct qmc_launch_args {
     const uint32_t *texp;    // [n_terms] packed exponents of U and F terms
     const double *texpd;     // [n_terms][QMC_DMAX] the same exponents as doubles
     const uint32_t *tprog;   // [n_terms][2] each term as two 4-factor words
+    const uint32_t *toff;    // [2][n_terms][4] LDS byte offsets of the terms' factors 1-4, 5-8
     const uint32_t *dprog;   // [n_dterms][2] the same for the derivative terms
     const double *tcoef;     // [n_points][n_terms] coefficients at each point
     const uint32_t *dexp;    // [n_dterms] packed exponents of derivative terms

@@ -339,7 +339,7 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                 return set_err(ctx, QMC_EINVAL, "sector %d: empty polynomial", s);
             }
             bool has_const = false;
-            std::vector<std::pair<int, int>> order;   // (mask, term)
+            std::vector<std::pair<int, int>> order;   // (mask * 4 + kind, term)
             for (int a = 0; a < P.n_terms; ++a) {
                 const uint8_t *e = P.exps + (size_t)a * S.dim;
                 bool zero = true;
@@ -355,7 +355,12 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                 for (int j = 0; j < h.ks; ++j)
                     if (e[perm[j]]) mask |= 1 << j;
                 has_const |= zero;
-                order.push_back({mask, a});
+                // kind: 0 at most four power-table factors, 1 five to
+                // eight, 2 the exp form
+                uint32_t w[2];
+                term_program(pack_exps(e, perm, S.dim), w);
+                const int kind = (w[0] >> 31) ? 2 : ((w[0] >> 30) & 1u) ? 1 : 0;
+                order.push_back({mask * 4 + kind, a});
             }
             if (!has_const) {
                 delete plan;
@@ -367,10 +372,20 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                                  return x.first < y.first;
                              });
             int32_t *rng = which == 0 ? h.um : h.fm;
-            int cursor = 0;
+            int32_t *rng1 = which == 0 ? h.um1 : h.fm1;
+            int32_t *rng2 = which == 0 ? h.um2 : h.fm2;
+            const int32_t base = (int32_t)plan->texp.size();
+            auto first_at_least = [&](int key) {
+                int c = 0;
+                while (c < (int)order.size() && order[c].first < key) ++c;
+                return base + c;
+            };
             for (int m = 0; m <= QMC_NMASK; ++m) {
-                while (cursor < (int)order.size() && order[cursor].first < m) ++cursor;
-                rng[m] = (int32_t)plan->texp.size() + cursor;
+                rng[m] = first_at_least(4 * m);
+                if (m < QMC_NMASK) {
+                    rng1[m] = first_at_least(4 * m + 1);
+                    rng2[m] = first_at_least(4 * m + 2);
+                }
             }
             for (auto &pr : order) {
                 const uint8_t *e = P.exps + (size_t)pr.second * S.dim;
@@ -463,6 +478,19 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_texpd, sizeof(double) * texpd.size());
     if (rc == QMC_OK)
         rc = qmc_dev_alloc(ctx, (void **)&plan->d_tprog, sizeof(uint32_t) * tprog.size());
+    // every factor of a term as the byte offset of its power-table slot in
+    // a lane's column (slot stride QMC_BLOCK elements of the plan's type)
+    const uint32_t esize = o.precision == QMC_FP32_EVAL ? 4u : 8u;
+    // first all terms' factors 1-4, then all terms' factors 5-8
+    const size_t nterm = plan->texp.size();
+    std::vector<uint32_t> toff(nterm * 8);
+    for (size_t t = 0; t < nterm; ++t)
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t slot = (tprog[2 * t + k / 4] >> (5 * (k % 4))) & 31u;
+            toff[(k / 4) * nterm * 4 + 4 * t + (k % 4)] = slot * QMC_BLOCK * esize;
+        }
+    if (rc == QMC_OK)
+        rc = qmc_dev_alloc(ctx, (void **)&plan->d_toff, sizeof(uint32_t) * toff.size());
     std::vector<uint32_t> dprog(plan->dexp.size() * 2);
     for (size_t t = 0; t < plan->dexp.size(); ++t) term_program(plan->dexp[t], &dprog[2 * t]);
     if (rc == QMC_OK && !dprog.empty())
@@ -487,6 +515,9 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                       hipMemcpyHostToDevice);
     if (e == hipSuccess && !dprog.empty())
         e = hipMemcpy(plan->d_dprog, dprog.data(), sizeof(uint32_t) * dprog.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(plan->d_toff, toff.data(), sizeof(uint32_t) * toff.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         qmc_plan_free(plan);
@@ -513,6 +544,12 @@ qmc_sec_dev qmc_sec_host::dev() const
     for (int m = 0; m <= QMC_NMASK; ++m) {
         d.um[m] = um[m];
         d.fm[m] = fm[m];
+    }
+    for (int m = 0; m < QMC_NMASK; ++m) {
+        d.um1[m] = um1[m];
+        d.um2[m] = um2[m];
+        d.fm1[m] = fm1[m];
+        d.fm2[m] = fm2[m];
     }
     for (int j = 0; j <= QMC_DMAX; ++j) d.d1[j] = d1[j];
     for (int j = 0; j <= QMC_DMAX * (QMC_DMAX + 1) / 2; ++j) d.d2[j] = d2[j];
@@ -547,6 +584,7 @@ extern "C" void qmc_plan_free(qmc_plan *plan)
     qmc_dev_free(ctx, plan->d_texp, sizeof(uint32_t) * plan->texp.size());
     qmc_dev_free(ctx, plan->d_texpd, sizeof(double) * plan->texp.size() * QMC_DMAX);
     qmc_dev_free(ctx, plan->d_tprog, sizeof(uint32_t) * plan->texp.size() * 2);
+    qmc_dev_free(ctx, plan->d_toff, sizeof(uint32_t) * plan->texp.size() * 8);
     qmc_dev_free(ctx, plan->d_dprog, sizeof(uint32_t) * plan->dexp.size() * 2);
     qmc_dev_free(ctx, plan->d_dexp, sizeof(uint32_t) * plan->dexp.size());
     delete plan;
@@ -894,6 +932,7 @@ hipError_t qmc_enqueue(qmc_job *job, bool timing)
     A.texp = plan->d_texp;
     A.texpd = plan->d_texpd;
     A.tprog = plan->d_tprog;
+    A.toff = plan->d_toff;
     A.dprog = plan->d_dprog;
     A.tcoef = job->d_coef;
     A.dexp = plan->d_dexp;
@@ -1223,7 +1262,7 @@ extern "C" int qmc_math_eval(qmc_ctx *ctx, int32_t fn, const double *x, double *
                              int64_t n)
 {
     if (!ctx) return QMC_EINVAL;
-    if (n < 0 || fn < QMC_MATH_LN || fn > QMC_MATH_EXPM1 || (n > 0 && (!x || !y)))
+    if (n < 0 || fn < QMC_MATH_LN || fn > QMC_MATH_RCP || (n > 0 && (!x || !y)))
         return set_err(ctx, QMC_EINVAL, "qmc_math_eval: bad argument");
     (void)hipSetDevice(ctx->device);
     HIP_CHECK(ctx, qmc_launch_math(fn, x, y, (long)n, ctx->stream));

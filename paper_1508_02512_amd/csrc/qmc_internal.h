@@ -49,6 +49,8 @@ struct qmc_sec_host {
     double a[QMC_DMAX] = {}, b[QMC_DMAX] = {}, inv_b[QMC_DMAX] = {};
     int aint[QMC_DMAX] = {};
     int32_t um[QMC_NMASK + 1] = {}, fm[QMC_NMASK + 1] = {};
+    int32_t um1[QMC_NMASK] = {}, um2[QMC_NMASK] = {};
+    int32_t fm1[QMC_NMASK] = {}, fm2[QMC_NMASK] = {};
     int32_t d1[QMC_DMAX + 1] = {};
     int32_t d2[QMC_DMAX * (QMC_DMAX + 1) / 2 + 1] = {};
     double u0 = 0, u1 = 0, f0 = 0, f1 = 0;
@@ -85,6 +87,7 @@ struct qmc_plan {
     uint32_t *d_texp = nullptr;
     double *d_texpd = nullptr;
     uint32_t *d_tprog = nullptr;
+    uint32_t *d_toff = nullptr;      // [2][n_terms][4] power-table byte offsets
     uint32_t *d_dprog = nullptr;
     uint32_t *d_dexp = nullptr;
 };

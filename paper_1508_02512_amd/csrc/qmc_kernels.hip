@@ -83,7 +83,8 @@ __global__ void qmc_math_kernel(int fn, const double *x, double *y, long n)
     case 0: r = qmc_math::ln(v); break;
     case 1: r = qmc_math::ln1p(v); break;
     case 2: r = qmc_math::ex(v); break;
-    default: r = qmc_math::exm1(v); break;
+    case 3: r = qmc_math::exm1(v); break;
+    default: r = qmc_math::rcp(v); break;
     }
     y[i] = r;
 }

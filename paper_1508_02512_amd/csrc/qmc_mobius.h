@@ -28,15 +28,8 @@
 
 namespace mobius {
 
-// reciprocal to ~1 ulp: hardware estimate and Newton steps
-__device__ __forceinline__ double rcp(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
+// reciprocal to ~1 ulp: the library's (hardware estimate, two Newton steps)
+__device__ __forceinline__ double rcp(double x) { return qmc_math::rcp(x); }
 
 __device__ __forceinline__ float rcp(float x)
 {

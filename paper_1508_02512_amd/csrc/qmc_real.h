@@ -65,6 +65,48 @@ __device__ __forceinline__ T tmono_log(cptr<double> e, const T *lt, int d)
     return qmc_math::ex(x);
 }
 
+// sum_q c_q prod_j t_j^e_jq over one pole-mask group of terms: [q0, q1)
+// with at most four power-table factors, [q1, q2) with five to eight,
+// [q2, q3) in the exp form.  Factors are read from this lane's column of
+// the power table at the byte offsets the planner stored per term (toff:
+// the first four factors of every term, toff2: the next four), so the loops
+// carry no branch and no decoding.  Terms of the first kind go in blocks of
+// four: their 16 offsets arrive in one scalar load and their 16 LDS reads
+// are in flight together.
+template <typename T>
+__device__ __forceinline__ T prod4_at(const char *colb, cptr<uint32_t> o)
+{
+    const T a = *(const T *)(colb + o[0]);
+    const T b = *(const T *)(colb + o[1]);
+    const T c = *(const T *)(colb + o[2]);
+    const T e = *(const T *)(colb + o[3]);
+    return (a * b) * (c * e);
+}
+
+template <typename T>
+__device__ __forceinline__ T poly_group(int q0, int q1, int q2, int q3, cptr<uint32_t> toff,
+                                        cptr<uint32_t> toff2, cptr<double> coef,
+                                        const char *colb, cptr<double> texpd, const T *lt,
+                                        int d)
+{
+    T s = 0;
+    int q = q0;
+    for (; q + 4 <= q1; q += 4) {
+        cptr<uint32_t> o = toff + 4 * q;
+        T v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = *(const T *)(colb + o[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            s = fma(T(coef[q + k]), (v[4 * k] * v[4 * k + 1]) * (v[4 * k + 2] * v[4 * k + 3]), s);
+    }
+    for (; q < q1; ++q) s = fma(T(coef[q]), prod4_at<T>(colb, toff + 4 * q), s);
+    for (; q < q2; ++q)
+        s = fma(T(coef[q]), prod4_at<T>(colb, toff + 4 * q) * prod4_at<T>(colb, toff2 + 4 * q), s);
+    for (; q < q3; ++q) s = fma(T(coef[q]), tmono_log<T>(texpd + q * QMC_DMAX, lt, d), s);
+    return s;
+}
+
 template <typename T>
 __device__ __forceinline__ T tpowi(T x, int e)
 {
@@ -318,7 +360,8 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
     cptr<double> coef = ro(A.tcoef) + (size_t)it.point * A.n_terms;
     cptr<double> shift = ro(A.shifts) + it.shift * QMC_DMAX;
     cptr<double> texpd = ro(A.texpd);
-    cptr<uint32_t> tprog = ro(A.tprog);
+    cptr<uint32_t> toff = ro(A.toff);
+    cptr<uint32_t> toff2 = ro(A.toff) + (size_t)4 * A.n_terms;
     const int r = A.korobov_r;
 
     constexpr bool LDS = lds_sums<KS, K, T>();
@@ -410,23 +453,13 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                     }
                 }
                 // U and F: one pass over the terms grouped by pole mask
+                const char *colb = (const char *)col;
 #pragma unroll
                 for (int m = 0; m < (1 << KS); ++m) {
-                    T su = 0, sf = 0;
-                    for (int q = S->um[m]; q < S->um[m + 1]; ++q) {
-                        const T mono = (tprog[2 * q] >> 31)
-                                           ? tmono_log<T>(texpd + q * QMC_DMAX, lt, d)
-                                           : tmono_lds<T>(tprog + 2 * q, col);
-                        su = fma(T(coef[q]), mono, su);
-                    }
-                    for (int q = S->fm[m]; q < S->fm[m + 1]; ++q) {
-                        const T mono = (tprog[2 * q] >> 31)
-                                           ? tmono_log<T>(texpd + q * QMC_DMAX, lt, d)
-                                           : tmono_lds<T>(tprog + 2 * q, col);
-                        sf = fma(T(coef[q]), mono, sf);
-                    }
-                    P.SU[m] = su;
-                    P.SF[m] = sf;
+                    P.SU[m] = poly_group<T>(S->um[m], S->um1[m], S->um2[m], S->um[m + 1], toff,
+                                            toff2, coef, colb, texpd, lt, d);
+                    P.SF[m] = poly_group<T>(S->fm[m], S->fm1[m], S->fm2[m], S->fm[m + 1], toff,
+                                            toff2, coef, colb, texpd, lt, d);
                 }
                 T g[K];
                 if constexpr (use_mobius<T, KS>()) {

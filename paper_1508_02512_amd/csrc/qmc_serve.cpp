@@ -526,6 +526,7 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act, std::vector<Reques
         A.texp = P->d_texp;
         A.texpd = P->d_texpd;
         A.tprog = P->d_tprog;
+        A.toff = P->d_toff;
         A.dprog = P->d_dprog;
         A.tcoef = (const double *)pp.coef.p;
         A.dexp = P->d_dexp;

@@ -21,7 +21,7 @@ ERRORS = {-1: "QMC_EINVAL", -2: "QMC_EUNREGULATED", -3: "QMC_EUNSUPPORTED",
           -4: "QMC_ENOMEM", -5: "QMC_EBUDGET", -6: "QMC_EDEFORM",
           -7: "QMC_ENOTCONVERGED", -8: "QMC_EDEVICE", -9: "QMC_ECANCELLED"}
 QMC_FP64, QMC_FP32_EVAL = 0, 1
-QMC_MATH_LN, QMC_MATH_LN1P, QMC_MATH_EXP, QMC_MATH_EXPM1 = 0, 1, 2, 3
+QMC_MATH_LN, QMC_MATH_LN1P, QMC_MATH_EXP, QMC_MATH_EXPM1, QMC_MATH_RCP = 0, 1, 2, 3, 4
 QMC_MAX_DIM = 8
 QMC_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 

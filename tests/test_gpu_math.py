@@ -25,6 +25,9 @@ def _samples(fn, rng, n=1 << 20):
     elif fn == qmc.QMC_MATH_EXP:
         parts = [u(-700, 700, n), u(-1, 1, n), 10.0 ** u(-300, 0, n) * rng.choice([-1, 1], n),
                  np.log(2.0) / 2 * (1.0 + u(-1e-9, 1e-9, n)) * rng.choice([-1, 1], n)]
+    elif fn == qmc.QMC_MATH_RCP:
+        parts = [10.0 ** u(-300, 300, n) * rng.choice([-1, 1], n), u(0.5, 2.0, n),
+                 1.0 + u(-1e-12, 1e-12, n), u(1.0, 3.0, n)]
     else:
         parts = [u(-40, 40, n), 10.0 ** u(-300, 0, n) * rng.choice([-1, 1], n),
                  np.log(2.0) / 2 * (1.0 + u(-1e-9, 1e-9, n)) * rng.choice([-1, 1], n),
@@ -36,11 +39,13 @@ def _samples(fn, rng, n=1 << 20):
 def _reference(fn, x):
     xl = x.astype(np.longdouble)
     return {qmc.QMC_MATH_LN: np.log, qmc.QMC_MATH_LN1P: np.log1p,
-            qmc.QMC_MATH_EXP: np.exp, qmc.QMC_MATH_EXPM1: np.expm1}[fn](xl)
+            qmc.QMC_MATH_EXP: np.exp, qmc.QMC_MATH_EXPM1: np.expm1,
+            qmc.QMC_MATH_RCP: lambda v: 1 / v}[fn](xl)
 
 
 @pytest.mark.parametrize("fn,bound_ulp", [(qmc.QMC_MATH_LN, 2.0), (qmc.QMC_MATH_LN1P, 3.0),
-                                          (qmc.QMC_MATH_EXP, 2.0), (qmc.QMC_MATH_EXPM1, 3.0)])
+                                          (qmc.QMC_MATH_EXP, 2.0), (qmc.QMC_MATH_EXPM1, 3.0),
+                                          (qmc.QMC_MATH_RCP, 2.0)])
 def test_relative_error(fn, bound_ulp):
     print(f"math: fn {fn}", flush=True)
     rng = np.random.default_rng(fn)
@@ -66,6 +71,6 @@ def test_relative_error(fn, bound_ulp):
 
 def test_bad_arguments_raise():
     with pytest.raises(qmc.QMCError):
-        ctx().math_eval(7, 0, 0, 1)
+        ctx().math_eval(9, 0, 0, 1)
     with pytest.raises(qmc.QMCError):
         ctx().math_eval(0, 0, 0, -1)
