@@ -105,12 +105,13 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(poles, width, n, m):
+def measured_traffic(poles, width, n, m, ppl, variant):
     """HBM bytes (read + written) per launch of one integrand kernel class of
-    this workload, from the rocprofv3 FETCH_SIZE and WRITE_SIZE passes
-    recorded in profiles/traffic.json (each calibrated with a 256 MiB device
-    copy).  None when no pass was taken for that class, or when the kernel
-    sources changed since the counters were taken."""
+    this workload in one launch shape (points per lane, occupancy build),
+    from the rocprofv3 FETCH_SIZE and WRITE_SIZE passes recorded in
+    profiles/traffic.json (each calibrated with a 256 MiB device copy).  None
+    when no pass was taken for that launch, or when the kernel sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -120,9 +121,10 @@ def measured_traffic(poles, width, n, m):
     if rec.get("source_hash") != kernel_source_hash():
         return None, "counters predate the current kernel sources"
     for e in rec.get("entries", []):
-        if (e["poles"], e["width"], e["n"], e["m"]) == (poles, width, n, m):
+        if (e["poles"], e["width"], e["n"], e["m"], e.get("points_per_lane"),
+                e.get("variant")) == (poles, width, n, m, ppl, variant):
             return e["read_bytes"] + e["write_bytes"], "rocprofv3 FETCH_SIZE + WRITE_SIZE"
-    return None, "class not in the counter record"
+    return None, "launch shape not in the counter record"
 
 
 def parse():
@@ -136,6 +138,8 @@ def parse():
     ap.add_argument("--no-time-to-target", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="bind the main workload with the library's default launch shapes")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the non-planar vertex, the 512-point batch and the s-scan")
     ap.add_argument("--copy-probe", action="store_true",
@@ -528,10 +532,17 @@ def main():
     plan = ctx.plan(arrs, info, 0, fe.prefactor_series(info, 12))
     kin = fe.kin_vector(info, kin_vals)
     n, m = args.n, args.shifts
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    tuned = None
+    if not args.no_autotune:
+        # launch shape per kernel class (points per lane, persistent grid,
+        # occupancy build) timed on the same lattice with 4 shifts
+        t_tune = time.perf_counter()
+        tuned = plan.autotune(kin, (n, lattice(n)), shift_table(0, 4, 8))
+        log(f"autotune ({time.perf_counter() - t_tune:.1f} s): {tuned}")
     job = plan.bind(kin, (n, lattice(n)), shift_table(0, m, 8))
     job.profile(True)          # HIP events around every kernel-class launch
 
-    log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"bench: {plan.n_sectors} sectors, n={n}, m={m}, warmup {args.warmup}")
     for _ in range(args.warmup):
         job.run()
@@ -608,6 +619,9 @@ def main():
     if not args.no_fp32:
         plan32 = ctx.plan(arrs, info, 0, fe.prefactor_series(info, 12),
                           precision=qmc.QMC_FP32_EVAL)
+        tuned32 = None
+        if not args.no_autotune:
+            tuned32 = plan32.autotune(kin, (n, lattice(n)), shift_table(0, 4, 8))
         job32 = plan32.bind(kin, (n, lattice(n)), shift_table(0, m, 8))
         job32.run()
         job32.fetch()
@@ -628,6 +642,7 @@ def main():
                 "ms_per_step": wall32 / args.steps * 1e3,
                 "kernel_ms_per_step": float(np.mean(k32)),
                 "achieved_tflops": res32["algo_flops"] / (float(np.mean(k32)) / 1e3) / 1e12,
+                "autotune": tuned32,
                 "max_dev_vs_fp64_in_sigma": float(dev.max()),
                 "rel_dev_vs_fp64_per_order": [float(x) for x in rel]}
         if not args.no_time_to_target:
@@ -652,7 +667,8 @@ def main():
     if not args.no_serve:
         serve = serve_suite(qmc, fe, PROBLEMS, lattice, args, log)
 
-    traffic, traffic_src = measured_traffic(dom_stat["poles"], dom_stat["width"], n, m)
+    traffic, traffic_src = measured_traffic(dom_stat["poles"], dom_stat["width"], n, m,
+                                            dom_stat["points_per_lane"], dom_stat["variant"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -669,7 +685,8 @@ def main():
         "config": {"workload": "planar double box (7 props, 6 dims), Euclidean "
                                "s=-3 t=-1, all sectors, eps^-4..eps^0, Korobov r=2",
                    "sectors": plan.n_sectors, "lattice_n": n, "shifts": m,
-                   "evals_per_step": evals_per_step, "precision": "fp64"},
+                   "evals_per_step": evals_per_step, "precision": "fp64",
+                   "autotune": tuned},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
                      "traffic": traffic, "traffic_source": traffic_src,
@@ -680,6 +697,7 @@ def main():
                      "launch_ms": dom_ms, "algo_flops_per_launch": dom_stat["algo_flops"],
                      "evals_per_launch": dom_stat["evals"],
                      "grid": dom_stat["grid"], "points_per_lane": dom_stat["points_per_lane"],
+                     "occupancy_variant": dom_stat["variant"],
                      "step": {"kernel_ms": avg_kernel_s * 1e3,
                               "algo_flops": res["algo_flops"],
                               "achieved": achieved_step / 1e12,
