@@ -24,6 +24,7 @@ from fractions import Fraction
 import mpmath
 import numpy as np
 
+from . import ibp
 from .decompose import decompose
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,7 +44,11 @@ class _Sector(ctypes.Structure):
                 ("eF", ctypes.POINTER(ctypes.c_int32)),
                 ("cF", ctypes.POINTER(ctypes.c_double)),
                 ("u0", ctypes.c_double), ("u1", ctypes.c_double),
-                ("f0", ctypes.c_double), ("f1", ctypes.c_double)]
+                ("f0", ctypes.c_double), ("f1", ctypes.c_double),
+                ("nP", ctypes.c_int),
+                ("nPt", ctypes.POINTER(ctypes.c_int32)),
+                ("eP", ctypes.POINTER(ctypes.c_int32)),
+                ("cP", ctypes.POINTER(ctypes.c_double))]
 
 
 def build() -> str:
@@ -105,9 +110,18 @@ class NumericSector:
         self.cU = np.array([form_value(sec["U"][tuple(e)], kin) for e in self.eU])
         self.eF = np.array(sorted(sec["F"]), dtype=np.int32).reshape(-1, d)
         self.cF = np.array([form_value(sec["F"][tuple(e)], kin) for e in self.eF])
-        self.u = (float(info["u0"]), float(info["u1"]))
-        self.f = (float(info["f0"]), float(info["f1"]))
+        u = sec.get("u", (info["u0"], info["u1"]))
+        f = sec.get("f", (info["f0"], info["f1"]))
+        self.u = (float(u[0]), float(u[1]))
+        self.f = (float(f[0]), float(f[1]))
         self.nJ = int(np.sum(self.a == -1.0))
+        # numerator factors (Eq. 13), all terms of all factors in one table
+        P = sec.get("P", [])
+        self.nPt = np.array([len(p) for p in P] or [0], dtype=np.int32)
+        eP = [e for p in P for e in sorted(p)]
+        self.eP = np.array(eP or [[0] * d], dtype=np.int32).reshape(-1, d)
+        self.cP = np.array([form_value(p[e], kin) for p in P for e in sorted(p)] or [0.0])
+        self.nP = len(P)
 
     def cstruct(self):
         s = _Sector()
@@ -118,6 +132,10 @@ class NumericSector:
         s.eF, s.cF = _ptr(self.eF, ctypes.c_int32), _ptr(self.cF, ctypes.c_double)
         s.u0, s.u1 = self.u
         s.f0, s.f1 = self.f
+        s.nP = self.nP
+        s.nPt = _ptr(self.nPt, ctypes.c_int32)
+        s.eP = _ptr(self.eP, ctypes.c_int32)
+        s.cP = _ptr(self.cP, ctypes.c_double)
         return s
 
 
@@ -203,13 +221,18 @@ def assemble(per_sector, D, pref, pref_lo, sec_lo, n, eps_lo, eps_hi):
     """Per-shift Laurent estimates, mean and error (Eqs. 18-20).
 
     per_sector: list of arrays [m][K] complex of raw sums (no 1/n), orders
-    sec_lo.. ; D: list of sector constants; pref: dict order->coeff.
+    sec_lo.. ; D: list of sector constants, each a number or a power series
+    {order >= 0: coefficient} in eps (the coefficient C(eps) of a sector
+    from Eq. 13); pref: dict order->coeff.
     """
     m = per_sector[0].shape[0]
     K = per_sector[0].shape[1]
     tot = np.zeros((m, K), dtype=complex)
     for S, Ds in zip(per_sector, D):
-        tot += Ds * S / float(n)
+        ser = Ds if isinstance(Ds, dict) else {0: Ds}
+        for e, c in ser.items():
+            if 0 <= e < K:
+                tot[:, e:] += complex(c) * S[:, :K - e] / float(n)
     orders = list(range(eps_lo, eps_hi + 1))
     Q = np.zeros((m, len(orders)), dtype=complex)
     for qi, p in enumerate(orders):
@@ -232,6 +255,8 @@ def integrate(problem, kin, n, z, shifts, r=2, lam=0.0, eps_hi=0, nthreads=0,
         sectors, info = decompose(problem)
     else:
         sectors, info = sectors
+    if ibp.needs_ibp(sectors):
+        sectors = ibp.expand(sectors, info)
     nums = [NumericSector(s, info, kin) for s in sectors]
     kmax = max(ns.nJ for ns in nums)
     pref_probe, pref_lo = gamma_prefactor(info, -2, eps_hi + kmax + 2)
@@ -246,8 +271,8 @@ def integrate(problem, kin, n, z, shifts, r=2, lam=0.0, eps_hi=0, nthreads=0,
         per.append(S)
         counts += c.sum(axis=0)
     eps_lo = sec_lo + pref_lo
-    res = assemble(per, [float(s.get("D", 1)) for s in sectors], pref_probe, pref_lo, sec_lo, n,
-                   eps_lo, eps_hi)
+    res = assemble(per, [s["C"] if "C" in s else float(s.get("D", 1)) for s in sectors],
+                   pref_probe, pref_lo, sec_lo, n, eps_lo, eps_hi)
     res["sector_sums"] = per
     res["counts"] = counts
     res["sec_lo"] = sec_lo

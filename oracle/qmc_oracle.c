@@ -5,8 +5,11 @@
  *
  * For one sector of the form of Eq. 9 (Section II),
  *
- *   I = int_[0,1]^d  prod_j t_j^(a_j + b_j eps)  U(t)^(u0 + u1 eps)  F(t)^(f0 + f1 eps) dt
+ *   I = int_[0,1]^d  prod_j t_j^(a_j + b_j eps)  P_1(t) .. P_r(t)
+ *                     U(t)^(u0 + u1 eps)  F(t)^(f0 + f1 eps) dt
  *
+ * (the numerator factors P_i, polynomials of any sign, come from the
+ * integration by parts of Eq. 13; r = 0 for the sectors of Eq. 9)
  * and every shift k it returns the shifted lattice sums (Section III,
  * Eqs. 17-18, before the 1/n)
  *
@@ -92,6 +95,10 @@ typedef struct {
     const int32_t *eF;
     const double *cF;
     double u0, u1, f0, f1;
+    int nP;                     /* numerator factors */
+    const int32_t *nPt;         /* [nP] terms of each factor */
+    const int32_t *eP;          /* [sum nPt][dim], factor by factor */
+    const double *cP;           /* [sum nPt] */
 } oracle_sector;
 
 /* A truncated Laurent series: c[q] is the coefficient of eps^(ORD_LO+q);
@@ -312,8 +319,11 @@ static void h_series(const lims *L, const oracle_sector *s, const real *tp,
         if (CIMAG(Fz) > 0) ++*bad_f;
         if (CREAL(Uz) <= 0) ++*bad_u;
     }
+    cplx num = 1;
+    for (int k = 0, off = 0; k < s->nP; off += s->nPt[k], ++k)
+        num *= poly_cplx(s->nPt[k], s->eP + (size_t)off * d, s->cP + off, d, z);
     series f;
-    s_const(h, detJ);
+    s_const(h, detJ * num);
     for (int j = 0; j < d; ++j) {
         if (inJ[j]) {
             if (lambda > 0.0) {

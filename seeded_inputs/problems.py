@@ -59,6 +59,50 @@ BUBBLE_MASSIVE = Problem(
     (_P([1], mass="msq"), _P([1], {"p": 1}, mass="msq")),
     note="equal-mass two-point function, threshold at s = 4 msq")
 
+# dotted propagators (powers nu > 1): their sectors carry t^(a + b eps) with
+# a < -1, which the integration by parts of Eq. 13 reduces
+BUBBLE_DOT = Problem(
+    "bubble_dot", 1, ("p",), ("s",),
+    {("p", "p"): {"s": "1"}},
+    (_P([1]), _P([1], {"p": 1}, power=3)),
+    note="massless two-point function with powers (1, 3)")
+
+BUBBLE_DOT23 = Problem(
+    "bubble_dot23", 1, ("p",), ("s",),
+    {("p", "p"): {"s": "1"}},
+    (_P([1], power=2), _P([1], {"p": 1}, power=3)),
+    note="massless two-point function with powers (2, 3)")
+
+BUBBLE_DOT14 = Problem(
+    "bubble_dot14", 1, ("p",), ("s",),
+    {("p", "p"): {"s": "1"}},
+    (_P([1]), _P([1], {"p": 1}, power=4)),
+    note="massless two-point function with powers (1, 4)")
+
+BUBBLE_MASSIVE_DOT = Problem(
+    "bubble_massive_dot", 1, ("p",), ("s", "msq"),
+    {("p", "p"): {"s": "1"}},
+    (_P([1], mass="msq"), _P([1], {"p": 1}, power=3)),
+    note="two-point function, one massive propagator and one massless cubed")
+
+SUNSET_DOT = Problem(
+    "sunset_dot", 2, ("p",), ("s",),
+    {("p", "p"): {"s": "1"}},
+    (_P([1, 0]), _P([0, 1]), _P([1, 1], {"p": -1}, power=3)),
+    note="massless two-loop sunset with powers (1, 1, 3)")
+
+SUNSET_DOT114 = Problem(
+    "sunset_dot114", 2, ("p",), ("s",),
+    {("p", "p"): {"s": "1"}},
+    (_P([1, 0]), _P([0, 1]), _P([1, 1], {"p": -1}, power=4)),
+    note="massless two-loop sunset with powers (1, 1, 4)")
+
+SUNSET_DOT123 = Problem(
+    "sunset_dot123", 2, ("p",), ("s",),
+    {("p", "p"): {"s": "1"}},
+    (_P([1, 0]), _P([0, 1], power=2), _P([1, 1], {"p": -1}, power=3)),
+    note="massless two-loop sunset with powers (1, 2, 3)")
+
 # all momenta incoming, p4 = -p1-p2-p3, s = (p1+p2)^2, t = (p2+p3)^2
 _SP_MASSLESS_4PT = {
     ("p1", "p1"): {}, ("p2", "p2"): {}, ("p3", "p3"): {},
@@ -81,6 +125,19 @@ TRIANGLE_OFFSHELL = Problem(
      ("p1", "p2"): {"p3sq": "1/2", "p1sq": "-1/2", "p2sq": "-1/2"}},
     (_P([1]), _P([1], {"p1": 1}), _P([1], {"p1": 1, "p2": 1})),
     note="one-loop massless triangle, three off-shell legs")
+
+BOX_DOT = Problem(
+    "box_dot", 1, ("p1", "p2", "p3"), ("s", "t"), _SP_MASSLESS_4PT,
+    (_P([1], power=2), _P([1], {"p1": 1}), _P([1], {"p1": 1, "p2": 1}),
+     _P([1], {"p1": 1, "p2": 1, "p3": 1})),
+    note="massless on-shell box with the first propagator squared")
+
+TRIANGLE_OFFSHELL_DOT = Problem(
+    "triangle_offshell_dot", 1, ("p1", "p2"), ("p1sq", "p2sq", "p3sq"),
+    {("p1", "p1"): {"p1sq": "1"}, ("p2", "p2"): {"p2sq": "1"},
+     ("p1", "p2"): {"p3sq": "1/2", "p1sq": "-1/2", "p2sq": "-1/2"}},
+    (_P([1], power=3), _P([1], {"p1": 1}), _P([1], {"p1": 1, "p2": 1})),
+    note="off-shell massless triangle, first propagator cubed")
 
 # --- two loops ----------------------------------------------------------------
 
@@ -205,6 +262,9 @@ HH_NONPLANAR = Problem(
 HH_POINT = {"s": 160000.0, "t": -6000.0, "mtsq": 172.0 ** 2, "mhsq": 125.0 ** 2}
 
 PROBLEMS = {p.name: p for p in (BUBBLE, BUBBLE_MASSIVE, BOX, TRIANGLE_OFFSHELL,
+                                BUBBLE_DOT, BUBBLE_DOT23, BUBBLE_DOT14, BUBBLE_MASSIVE_DOT,
+                                SUNSET_DOT, SUNSET_DOT114, SUNSET_DOT123, BOX_DOT,
+                                TRIANGLE_OFFSHELL_DOT,
                                 DOUBLEBOX,
                                 DOUBLEBOX_OFFSHELL, DOUBLEBOX_OFF14,
                                 DOUBLEBOX_OFF24, DOUBLEBOX_OFF34,
