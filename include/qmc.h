@@ -46,8 +46,10 @@ extern "C" {
 #define QMC_OK 0
 #define QMC_PENDING 1            /* request still running (qmc_poll/qmc_wait) */
 #define QMC_EINVAL (-1)          /* bad sizes, exponents, missing constant term, m < 2 */
-#define QMC_EUNREGULATED (-2)    /* a_j = -1 with b_j = 0 (pole not regulated) */
-#define QMC_EUNSUPPORTED (-3)    /* a_j < -1, too many poles or orders, dim > QMC_MAX_DIM */
+#define QMC_EUNREGULATED (-2)    /* a_j = -1 with b_j = 0 (pole not regulated), also when
+                                    reached by integration by parts */
+#define QMC_EUNSUPPORTED (-3)    /* too many poles, orders or numerator factors, dim >
+                                    QMC_MAX_DIM, integration by parts with lambda > 0 */
 #define QMC_ENOMEM (-4)          /* host or device allocation failed */
 #define QMC_EBUDGET (-5)         /* request does not fit the HBM budget */
 #define QMC_EDEFORM (-6)         /* Im F(z) > 0, Re U(z) <= 0 or F <= 0 without deformation */
@@ -59,6 +61,7 @@ extern "C" {
 #define QMC_MAX_DIM 8            /* integration variables per sector */
 #define QMC_MAX_POLES 4          /* variables with a_j = -1 per sector */
 #define QMC_MAX_ORDERS 8         /* Laurent orders carried per sector */
+#define QMC_MAX_FACTORS 4        /* numerator factors per sector after Eq. 13 */
 #define QMC_MAX_EXP 15           /* largest exponent of a polynomial term */
 
 /* ---- precision modes ----------------------------------------------------- */
@@ -88,7 +91,11 @@ typedef struct {
 } qmc_poly;
 
 /* One sector (Eq. 9): D * prod_j t_j^(a_j + b_j eps) U^(u0 + u1 eps) F^(f0 + f1 eps).
- * a_j must be -1 (then b_j != 0; the pole is subtracted, Eq. 11) or > -1.
+ * a_j = -1 (then b_j != 0): the pole is subtracted (Eq. 11).  a_j < -1 (as
+ * dotted propagators give): the plan applies the integration by parts of
+ * Eq. 13 in that variable until its power is -1 or above -1, which turns
+ * the sector into several, with numerator factors (derivatives of U and F)
+ * and an eps-dependent coefficient each; Euclidean plans only (lambda = 0).
  * U and F must contain the all-zero exponent (their constant term). */
 typedef struct {
     int32_t dim;                 /* 1 .. QMC_MAX_DIM */
@@ -135,7 +142,27 @@ typedef struct {
     int32_t eps_lo, eps_hi;
     int32_t max_poles, deform;
     double flops_per_point;      /* algorithmic FP64 flops of one lattice point, summed over sectors */
+    int32_t n_input_sectors;     /* sectors given; n_sectors counts them after Eq. 13 */
+    int32_t max_factors;         /* most numerator factors of a sector (Eq. 13) */
 } qmc_plan_info;
+
+/* One planned sector, as the integration by parts of Eq. 13 left it:
+ *   C(eps) * prod_j t_j^(a_j + b_j eps) * P_1 .. P_r * U^(u0 + u1 eps) F^(f0 + f1 eps)
+ * over `dim` variables (the input sector's, minus those set to 1 by
+ * boundary terms; 1 dummy variable if none is left).  Planned sectors come
+ * in a fixed order: input sectors in order; within one, its variables in
+ * increasing index, each application of Eq. 13 giving the boundary term,
+ * then the derivative terms (numerator factors in order, then U, then F),
+ * each expanded completely before the next.  A sector without exponents
+ * below -1 is planned unchanged (C = D, no factor). */
+typedef struct {
+    int32_t origin;              /* index of the input sector */
+    int32_t dim;                 /* integration variables */
+    int32_t poles;               /* variables with a_j = -1 (Eq. 11) */
+    int32_t factors;             /* numerator factors r */
+    double u_exp[2], f_exp[2];   /* powers of U and F */
+    double coef[QMC_MAX_ORDERS][2];   /* C(eps) = sum_k coef[k] eps^k (re, im) */
+} qmc_sector_info;
 
 typedef struct {
     qmc_coeff *coeff;            /* [n_points][eps_hi-eps_lo+1] */
@@ -162,13 +189,18 @@ void qmc_destroy(qmc_ctx *ctx);
 int qmc_set_stream(qmc_ctx *ctx, void *hip_stream);
 const char *qmc_last_error(qmc_ctx *ctx);
 
-/* Validate the sectors, permute each sector's variables so the subtracted
- * ones come first, sort polynomial terms by which of those they contain,
- * derive dF and d2F tables when lambda > 0, and upload the tables. */
+/* Validate the sectors, apply Eq. 13 where some a_j < -1, permute each
+ * sector's variables so the subtracted ones come first, sort polynomial
+ * terms by which of those they contain, derive dF and d2F tables when
+ * lambda > 0, and upload the tables.  Everything sized "per sector" below
+ * (lat_per_sector, sector_sums, qmc_size_lattices) counts planned sectors,
+ * qmc_plan_info.n_sectors of them. */
 int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *problem,
                      const qmc_plan_opts *opts, qmc_plan **out);
 void qmc_plan_free(qmc_plan *plan);
 int qmc_plan_get_info(const qmc_plan *plan, qmc_plan_info *info);
+/* Planned sector s (0 <= s < n_sectors); QMC_EINVAL if out of range. */
+int qmc_plan_sector_info(const qmc_plan *plan, int32_t s, qmc_sector_info *out);
 
 /* Integrate at n_points kinematic points kin[n_points][n_inv] with the
  * lattice `lat` (or lat_per_sector[n_sectors] if not NULL) and the shifts

@@ -17,6 +17,8 @@
 #define QMC_BLOCK 256
 #define QMC_PROG_SLOTS 17    // power table slots: t_j, t_j^2 (j < 8) and 1
 #define QMC_NO_INT (-1000000)
+#define QMC_NFMAX 4          // numerator factors per sector (QMC_MAX_FACTORS)
+#define QMC_NCOEF 8          // length of a sector's coefficient series (QMC_MAX_ORDERS)
 
 struct qmc_sec_dev {
     int32_t dim;             // number of variables
@@ -40,6 +42,11 @@ struct qmc_sec_dev {
     int32_t u0i, f0i;        // u0, f0 as integers, or QMC_NO_INT
     double lambda;
     int32_t lnmask;          // bit j: the real kernel needs ln t_j
+    int32_t nf;              // numerator factors from integration by parts (Eq. 13)
+    // terms of numerator factor i and mask m: [pm[i][m], pm[i][m+1]), split
+    // by kind at pm1 and pm2 like the terms of U
+    int32_t pm[QMC_NFMAX][QMC_NMASK + 1];
+    int32_t pm1[QMC_NFMAX][QMC_NMASK], pm2[QMC_NFMAX][QMC_NMASK];
     int32_t pad;
 };
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <complex>
@@ -199,6 +200,9 @@ static double sector_flops(const qmc_sec_host &h, bool deform)
                             ? std::abs(h.u0i) + std::abs(h.f0i) + (h.f0i < 0 || h.u0i < 0 ? T : 0)
                             : T;
     f += corners * (2 * T + powc + 4 + 3.0 * (K - 1));
+    // numerator factors (Eq. 13): their terms are in term_nnz; one product
+    // per factor in the union algebra over the 2^ks subsets (3^ks terms)
+    f += h.nf * 2.0 * std::pow(3.0, ks);
     f += ks * (T + 3.0 * (K - 1));              // 1/t and (b ln t)^r / r!
     f += (corners - 1) * (K + K * (K - 1) + 3.0 * K);   // folds
     f += K * (2 + 4);                           // weight and Neumaier
@@ -248,37 +252,76 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
     plan->pref.assign(pb->prefactor, pb->prefactor + 2 * pb->n_pref);
     plan->n_pref = pb->n_pref;
 
-    const int ns = pb->n_sectors;
-    int max_ks = 0;
-    // pass 1: poles per sector
-    for (int s = 0; s < ns; ++s) {
+    // inputs: dimensions and finite exponents
+    for (int s = 0; s < pb->n_sectors; ++s) {
         const qmc_sector &S = pb->sectors[s];
         if (S.dim < 1 || S.dim > QMC_MAX_DIM || !S.mono_a || !S.mono_b) {
             delete plan;
             return set_err(ctx, QMC_EUNSUPPORTED, "sector %d: dim %d outside 1..%d", s, S.dim,
                            QMC_MAX_DIM);
         }
-        int ks = 0;
-        for (int j = 0; j < S.dim; ++j) {
-            const double a = S.mono_a[j], b = S.mono_b[j];
-            if (!std::isfinite(a) || !std::isfinite(b)) {
+        for (int j = 0; j < S.dim; ++j)
+            if (!std::isfinite(S.mono_a[j]) || !std::isfinite(S.mono_b[j])) {
                 delete plan;
                 return set_err(ctx, QMC_EINVAL, "sector %d: exponent not finite", s);
             }
-            if (a == -1.0) {
-                if (b == 0.0) {
+        for (int w = 0; w < 2; ++w) {
+            const qmc_poly &P = w == 0 ? S.U : S.F;
+            if (P.n_terms < 1 || !P.exps || !P.coef) {
+                delete plan;
+                return set_err(ctx, QMC_EINVAL, "sector %d: empty polynomial", s);
+            }
+            for (int t = 0; t < P.n_terms * S.dim; ++t)
+                if (P.exps[t] > QMC_MAX_EXP) {
                     delete plan;
-                    return set_err(ctx, QMC_EUNREGULATED, "sector %d var %d: a = -1, b = 0", s, j);
+                    return set_err(ctx, QMC_EUNSUPPORTED, "sector %d: exponent %d > %d", s,
+                                   P.exps[t], QMC_MAX_EXP);
+                }
+        }
+    }
+    // exponents below -1: integration by parts (Eq. 13)
+    std::vector<qmc_ibp_sec> xs;
+    {
+        char msg[256] = {};
+        const int rc = qmc_ibp_expand(pb, xs, msg, sizeof msg);
+        if (rc != QMC_OK) {
+            delete plan;
+            return set_err(ctx, rc, "%s", msg);
+        }
+    }
+    plan->n_input_sectors = pb->n_sectors;
+    const int ns = (int)xs.size();
+    int max_ks = 0;
+    // pass 1: poles and numerator factors per sector
+    for (int s = 0; s < ns; ++s) {
+        const qmc_ibp_sec &X = xs[s];
+        if (X.ibp && o.lambda > 0.0) {
+            delete plan;
+            return set_err(ctx, QMC_EUNSUPPORTED,
+                           "sector %d: integration by parts (exponent below -1) is supported "
+                           "for Euclidean plans only (lambda = 0)", X.origin);
+        }
+        if ((int)X.eP.size() > QMC_MAX_FACTORS) {
+            delete plan;
+            return set_err(ctx, QMC_EUNSUPPORTED,
+                           "sector %d: integration by parts needs %d numerator factors > %d",
+                           X.origin, (int)X.eP.size(), QMC_MAX_FACTORS);
+        }
+        int ks = 0;
+        for (int j = 0; j < X.dim; ++j) {
+            if (X.a[j] == -1.0) {
+                if (X.b[j] == 0.0) {
+                    delete plan;
+                    return set_err(ctx, QMC_EUNREGULATED, "sector %d var %d: a = -1, b = 0",
+                                   X.origin, j);
                 }
                 ++ks;
-            } else if (a < -1.0) {
-                delete plan;
-                return set_err(ctx, QMC_EUNSUPPORTED, "sector %d var %d: a = %g < -1", s, j, a);
             }
         }
         if (ks > QMC_MAX_POLES) {
             delete plan;
-            return set_err(ctx, QMC_EUNSUPPORTED, "sector %d: %d poles > %d", s, ks, QMC_MAX_POLES);
+            return set_err(ctx, QMC_EUNSUPPORTED, "sector %d: %d poles > %d", X.origin, ks,
+                           QMC_MAX_POLES);
         }
         max_ks = std::max(max_ks, ks);
     }
@@ -299,81 +342,64 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
 
     // pass 2: tables
     for (int s = 0; s < ns; ++s) {
-        const qmc_sector &S = pb->sectors[s];
+        const qmc_ibp_sec &X = xs[s];
         qmc_sec_host h{};
-        h.dim = S.dim;
+        h.dim = X.dim;
+        h.origin = X.origin;
         int perm[QMC_DMAX], np = 0;
-        for (int j = 0; j < S.dim; ++j)
-            if (S.mono_a[j] == -1.0) perm[np++] = j;
+        for (int j = 0; j < X.dim; ++j)
+            if (X.a[j] == -1.0) perm[np++] = j;
         h.ks = np;
-        for (int j = 0; j < S.dim; ++j)
-            if (S.mono_a[j] != -1.0) perm[np++] = j;
+        for (int j = 0; j < X.dim; ++j)
+            if (X.a[j] != -1.0) perm[np++] = j;
         h.K = h.ks + kb;
         h.deform = o.lambda > 0.0 ? 1 : 0;
         for (int j = 0; j < QMC_DMAX; ++j) {
-            h.perm[j] = j < S.dim ? perm[j] : 0;
-            h.a[j] = j < S.dim ? S.mono_a[perm[j]] : 0.0;
-            h.b[j] = j < S.dim ? S.mono_b[perm[j]] : 0.0;
+            h.perm[j] = j < X.dim ? perm[j] : 0;
+            h.a[j] = j < X.dim ? X.a[perm[j]] : 0.0;
+            h.b[j] = j < X.dim ? X.b[perm[j]] : 0.0;
             h.aint[j] = 0;
-            if (j < S.dim) {
+            if (j < X.dim) {
                 const double a = h.a[j];
                 if (a >= 0.0 && a <= 64.0 && a == std::floor(a)) h.aint[j] = (int)a;
                 else h.aint[j] = QMC_NO_INT;
             }
         }
         for (int j = 0; j < h.ks; ++j) h.inv_b[j] = 1.0 / h.b[j];
-        h.u0 = S.u_exp[0];
-        h.u1 = S.u_exp[1];
-        h.f0 = S.f_exp[0];
-        h.f1 = S.f_exp[1];
+        h.u0 = X.u0;
+        h.u1 = X.u1;
+        h.f0 = X.f0;
+        h.f1 = X.f1;
         auto as_int = [](double v) {
             return (v == std::floor(v) && std::fabs(v) <= 64.0) ? (int)v : QMC_NO_INT;
         };
         h.u0i = as_int(h.u0);
         h.f0i = as_int(h.f0);
-        // terms of U then F, each grouped by pole mask
-        for (int which = 0; which < 2; ++which) {
-            const qmc_poly &P = which == 0 ? S.U : S.F;
-            if (P.n_terms < 1 || !P.exps || !P.coef) {
-                delete plan;
-                return set_err(ctx, QMC_EINVAL, "sector %d: empty polynomial", s);
-            }
+        // terms of U, F and the numerator factors, each grouped by pole mask
+        // and, within a mask, by kind (0: at most four power-table factors,
+        // 1: five to eight, 2: the exp form)
+        auto add_group = [&](int n_terms, const uint8_t *exps, const double *coefs,
+                             int32_t *rng, int32_t *rng1, int32_t *rng2) {
             bool has_const = false;
             std::vector<std::pair<int, int>> order;   // (mask * 4 + kind, term)
-            for (int a = 0; a < P.n_terms; ++a) {
-                const uint8_t *e = P.exps + (size_t)a * S.dim;
+            for (int a = 0; a < n_terms; ++a) {
+                const uint8_t *e = exps + (size_t)a * X.dim;
                 bool zero = true;
                 int mask = 0;
-                for (int j = 0; j < S.dim; ++j) {
-                    if (e[j] > QMC_MAX_EXP) {
-                        delete plan;
-                        return set_err(ctx, QMC_EUNSUPPORTED, "sector %d: exponent %d > %d", s,
-                                       e[j], QMC_MAX_EXP);
-                    }
+                for (int j = 0; j < X.dim; ++j)
                     if (e[j]) zero = false;
-                }
                 for (int j = 0; j < h.ks; ++j)
                     if (e[perm[j]]) mask |= 1 << j;
                 has_const |= zero;
-                // kind: 0 at most four power-table factors, 1 five to
-                // eight, 2 the exp form
                 uint32_t w[2];
-                term_program(pack_exps(e, perm, S.dim), w);
+                term_program(pack_exps(e, perm, X.dim), w);
                 const int kind = (w[0] >> 31) ? 2 : ((w[0] >> 30) & 1u) ? 1 : 0;
                 order.push_back({mask * 4 + kind, a});
-            }
-            if (!has_const) {
-                delete plan;
-                return set_err(ctx, QMC_EINVAL, "sector %d: %s has no constant term", s,
-                               which == 0 ? "U" : "F");
             }
             std::stable_sort(order.begin(), order.end(),
                              [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
                                  return x.first < y.first;
                              });
-            int32_t *rng = which == 0 ? h.um : h.fm;
-            int32_t *rng1 = which == 0 ? h.um1 : h.fm1;
-            int32_t *rng2 = which == 0 ? h.um2 : h.fm2;
             const int32_t base = (int32_t)plan->texp.size();
             auto first_at_least = [&](int key) {
                 int c = 0;
@@ -388,37 +414,50 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                 }
             }
             for (auto &pr : order) {
-                const uint8_t *e = P.exps + (size_t)pr.second * S.dim;
-                plan->texp.push_back(pack_exps(e, perm, S.dim));
+                const uint8_t *e = exps + (size_t)pr.second * X.dim;
+                plan->texp.push_back(pack_exps(e, perm, X.dim));
                 uint32_t w[2];
                 term_program(plan->texp.back(), w);
                 if (w[0] >> 31) h.mono_log = true;
-                const double *c = P.coef + (size_t)pr.second * pb->n_inv;
+                const double *c = coefs + (size_t)pr.second * pb->n_inv;
                 plan->tcoef_rows.insert(plan->tcoef_rows.end(), c, c + pb->n_inv);
                 int nnz = 0;
-                for (int j = 0; j < S.dim; ++j) nnz += e[j] != 0;
+                for (int j = 0; j < X.dim; ++j) nnz += e[j] != 0;
                 h.term_nnz.push_back(nnz);
             }
+            return has_const;
+        };
+        const int nU = (int)X.cU.size() / pb->n_inv, nF = (int)X.cF.size() / pb->n_inv;
+        if (!add_group(nU, X.eU.data(), X.cU.data(), h.um, h.um1, h.um2) ||
+            !add_group(nF, X.eF.data(), X.cF.data(), h.fm, h.fm1, h.fm2)) {
+            delete plan;
+            return set_err(ctx, QMC_EINVAL, "sector %d: U or F has no constant term%s", X.origin,
+                           X.ibp ? " after integration by parts" : "");
         }
+        h.nf = (int)X.eP.size();
+        for (int i = 0; i < h.nf; ++i)
+            add_group((int)X.cP[i].size() / pb->n_inv, X.eP[i].data(), X.cP[i].data(), h.pm[i],
+                      h.pm1[i], h.pm2[i]);
+        h.C = X.C;
         if (h.deform) {
-            if (!qmc_cplx_supported(S.dim, h.ks, kb)) {
+            if (!qmc_cplx_supported(X.dim, h.ks, kb)) {
                 delete plan;
                 return set_err(ctx, QMC_EUNSUPPORTED,
                                "sector %d: deformation supports dim <= 6 with at most 2 poles "
                                "and 1-2 orders above them (dim <= 2: 1-3 orders); "
                                "got dim %d, %d poles, %d orders",
-                               s, S.dim, h.ks, kb);
+                               X.origin, X.dim, h.ks, kb);
             }
             h.lambda = o.lambda;
             // dF/dt_j and d2F/dt_j dt_k (permuted variables) as term lists
             auto add_term = [&](const uint8_t *e, const double *c, int dj, int dk, double fac) {
                 uint8_t ee[QMC_DMAX] = {};
-                for (int v = 0; v < S.dim; ++v) ee[v] = e[perm[v]];
+                for (int v = 0; v < X.dim; ++v) ee[v] = e[perm[v]];
                 if (dj >= 0) ee[dj] -= 1;
                 if (dk >= 0) ee[dk] -= 1;
                 uint32_t packed = 0;
                 int nnz = 0;
-                for (int v = 0; v < S.dim; ++v) {
+                for (int v = 0; v < X.dim; ++v) {
                     packed |= (uint32_t)ee[v] << (4 * v);
                     nnz += ee[v] != 0;
                 }
@@ -426,31 +465,31 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                 for (int i = 0; i < pb->n_inv; ++i) plan->dcoef_rows.push_back(fac * c[i]);
                 h.dterm_nnz.push_back(nnz);
             };
-            const qmc_poly &F = S.F;
+            const uint8_t *Fe = X.eF.data();
+            const double *Fc = X.cF.data();
             for (int j = 0; j <= QMC_DMAX; ++j) {
                 h.d1[j] = (int32_t)plan->dexp.size();
-                if (j >= S.dim || j == QMC_DMAX) continue;
-                for (int a = 0; a < F.n_terms; ++a) {
-                    const uint8_t *e = F.exps + (size_t)a * S.dim;
+                if (j >= X.dim || j == QMC_DMAX) continue;
+                for (int a = 0; a < nF; ++a) {
+                    const uint8_t *e = Fe + (size_t)a * X.dim;
                     const int ej = e[perm[j]];
-                    if (ej > 0) add_term(e, F.coef + (size_t)a * pb->n_inv, j, -1, ej);
+                    if (ej > 0) add_term(e, Fc + (size_t)a * pb->n_inv, j, -1, ej);
                 }
             }
             int idx = 0;
             for (int j = 0; j < QMC_DMAX; ++j)
                 for (int k = j; k < QMC_DMAX; ++k, ++idx) {
                     h.d2[idx] = (int32_t)plan->dexp.size();
-                    if (j >= S.dim || k >= S.dim) continue;
-                    for (int a = 0; a < F.n_terms; ++a) {
-                        const uint8_t *e = F.exps + (size_t)a * S.dim;
+                    if (j >= X.dim || k >= X.dim) continue;
+                    for (int a = 0; a < nF; ++a) {
+                        const uint8_t *e = Fe + (size_t)a * X.dim;
                         const int ej = e[perm[j]], ek = e[perm[k]];
                         const double fac = j == k ? (double)ej * (ej - 1) : (double)ej * ek;
-                        if (fac != 0.0) add_term(e, F.coef + (size_t)a * pb->n_inv, j, k, fac);
+                        if (fac != 0.0) add_term(e, Fc + (size_t)a * pb->n_inv, j, k, fac);
                     }
                 }
             h.d2[idx] = (int32_t)plan->dexp.size();
         }
-        h.D = std::complex<double>(S.coef_re, S.coef_im);
         h.flops = sector_flops(h, false);
         h.flops_deform = h.deform ? sector_flops(h, true) : h.flops;
         plan->flops_per_point += h.flops;
@@ -565,6 +604,14 @@ qmc_sec_dev qmc_sec_host::dev() const
     d.lnmask = 0;
     for (int j = 0; j < dim; ++j)
         if (mono_log || j < ks || b[j] != 0.0 || aint[j] == QMC_NO_INT) d.lnmask |= 1 << j;
+    d.nf = nf;
+    for (int i = 0; i < QMC_NFMAX; ++i) {
+        for (int m = 0; m <= QMC_NMASK; ++m) d.pm[i][m] = pm[i][m];
+        for (int m = 0; m < QMC_NMASK; ++m) {
+            d.pm1[i][m] = pm1[i][m];
+            d.pm2[i][m] = pm2[i][m];
+        }
+    }
     return d;
 }
 
@@ -602,6 +649,30 @@ extern "C" int qmc_plan_get_info(const qmc_plan *plan, qmc_plan_info *info)
     info->max_poles = plan->max_ks;
     info->deform = plan->opts.lambda > 0.0;
     info->flops_per_point = plan->flops_per_point;
+    info->n_input_sectors = plan->n_input_sectors;
+    int nf = 0;
+    for (const qmc_sec_host &h : plan->secs) nf = std::max(nf, h.nf);
+    info->max_factors = nf;
+    return QMC_OK;
+}
+
+extern "C" int qmc_plan_sector_info(const qmc_plan *plan, int32_t s, qmc_sector_info *out)
+{
+    if (!plan || !out || s < 0 || s >= (int32_t)plan->secs.size()) return QMC_EINVAL;
+    const qmc_sec_host &h = plan->secs[s];
+    *out = qmc_sector_info{};
+    out->origin = h.origin;
+    out->dim = h.dim;
+    out->poles = h.ks;
+    out->factors = h.nf;
+    out->u_exp[0] = h.u0;
+    out->u_exp[1] = h.u1;
+    out->f_exp[0] = h.f0;
+    out->f_exp[1] = h.f1;
+    for (size_t e = 0; e < h.C.size() && e < (size_t)QMC_MAX_ORDERS; ++e) {
+        out->coef[e][0] = h.C[e].real();
+        out->coef[e][1] = h.C[e].imag();
+    }
     return QMC_OK;
 }
 
@@ -663,7 +734,7 @@ hipError_t qmc_launch_class(const qmc_plan *plan, const qmc_class &c, const qmc_
     const int grid = qmc_class_grid(c);
     const bool fp32 = plan->opts.precision == QMC_FP32_EVAL;
     if (c.deform) return qmc_launch_cplx(c.dm, c.ks, c.kb, fp32, c.variant, A, grid, stream);
-    return qmc_launch_real(c.ks, c.kb, fp32, c.variant, A, grid, stream);
+    return qmc_launch_real(c.ks, c.kb, fp32, c.variant, c.num != 0, A, grid, stream);
 }
 
 void qmc_job_release(qmc_job *job)
@@ -685,14 +756,14 @@ void qmc_job_release(qmc_job *job)
     job->h_gviol = nullptr;
 }
 
-std::string qmc_tune_key(const qmc_plan *plan, int ks, int dm, uint64_t n)
+std::string qmc_tune_key(const qmc_plan *plan, int ks, int dm, int num, uint64_t n)
 {
     int lg = 0;
     while ((2ull << lg) <= n) ++lg;
     char buf[128];
     // keyed by the plan's id, never its address: a freed plan's address
     // can be reused by a later, different plan
-    snprintf(buf, sizeof buf, "%llu/%d/%d/%d/%d", (unsigned long long)plan->id, ks, dm,
+    snprintf(buf, sizeof buf, "%llu/%d/%d/%d/%d/%d", (unsigned long long)plan->id, ks, dm, num,
              plan->opts.precision, lg);
     return buf;
 }
@@ -780,12 +851,13 @@ int qmc_job_prepare(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32
     std::vector<int> key_of((size_t)n_points * ns);
     std::vector<double> &lam = H.lam;
     lam.assign((size_t)n_points * ns, 0.0);
-    std::vector<std::pair<int, int>> keys;     // (ks, dm or 0 for real) of every class
+    // (ks, dm or 0 for real, numerator factors or not) of every class
+    std::vector<std::array<int, 3>> keys;
     for (int p = 0; p < n_points; ++p)
         for (int s = 0; s < ns; ++s) {
             const int dm = qmc_sector_mode(plan, s, coef.data() + (size_t)p * nt,
                                            &lam[(size_t)p * ns + s]);
-            const std::pair<int, int> key{plan->secs[s].ks, dm};
+            const std::array<int, 3> key{plan->secs[s].ks, dm, plan->secs[s].nf > 0 ? 1 : 0};
             auto it = std::find(keys.begin(), keys.end(), key);
             if (it == keys.end()) {
                 keys.push_back(key);
@@ -798,8 +870,9 @@ int qmc_job_prepare(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32
     std::sort(order.begin(), order.end(), [&](int x, int y) { return keys[x] < keys[y]; });
     for (int ki : order) {
         qmc_class c{};
-        c.ks = keys[ki].first;
-        c.dm = keys[ki].second;
+        c.ks = keys[ki][0];
+        c.dm = keys[ki][1];
+        c.num = keys[ki][2];
         c.deform = c.dm != 0;
         c.kb = plan->kb;
         c.begin = (int)items.size();
@@ -807,7 +880,7 @@ int qmc_job_prepare(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32
         c.grid = grid_override > 0 ? grid_override * ctx->n_cu : 0;
         if (ppl_override <= 0 && plan->opts.points_per_lane <= 0) {
             std::lock_guard<std::mutex> g(ctx->tune_mu);
-            auto t = ctx->tuned.find(qmc_tune_key(plan, c.ks, c.dm, nmax_sec));
+            auto t = ctx->tuned.find(qmc_tune_key(plan, c.ks, c.dm, c.num, nmax_sec));
             if (t != ctx->tuned.end()) {
                 c.ppl = t->second.ppl;
                 c.grid = t->second.grid_per_cu * ctx->n_cu;
@@ -1020,7 +1093,12 @@ int qmc_assemble(const qmc_plan *plan, int n_points, int m, const std::vector<ui
                 for (int q = 0; q < h.K; ++q) {
                     const int order = q - h.ks;
                     const std::complex<double> v(g[2 * q], g[2 * q + 1]);
-                    tot[order - plan->sec_lo] += h.D * v / (double)nsec[s];
+                    // the sector's coefficient series C(eps) (D, or Eq. 13's)
+                    for (size_t e = 0; e < h.C.size(); ++e) {
+                        const int j = order + (int)e - plan->sec_lo;
+                        if (j >= K) break;
+                        if (h.C[e] != 0.0) tot[j] += h.C[e] * v / (double)nsec[s];
+                    }
                 }
             }
             for (int oi = 0; oi < no; ++oi) {
@@ -1312,7 +1390,7 @@ extern "C" int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *ki
                 float ms = 0.0f;
                 if (hipEventElapsedTime(&ms, job->ev_cls[i], job->ev_cls[i + 1]) != hipSuccess)
                     continue;
-                const std::string key = qmc_tune_key(plan, c.ks, c.dm, nmax);
+                const std::string key = qmc_tune_key(plan, c.ks, c.dm, c.num, nmax);
                 auto it = best.find(key);
                 if (it == best.end() || ms < it->second.first.ms) {
                     qmc_tune t;

@@ -17,6 +17,9 @@
 
 struct qmc_serve_state;
 
+static_assert(QMC_NFMAX == QMC_MAX_FACTORS, "numerator factor limits differ");
+static_assert(QMC_NCOEF == QMC_MAX_ORDERS, "coefficient series lengths differ");
+
 // Launch shape chosen by the autotuner for one kernel class.
 struct qmc_tune {
     int ppl = 0;                     // points per lane per work item
@@ -42,6 +45,29 @@ struct qmc_ctx {
     std::map<std::string, qmc_tune> tuned;   // autotuner results by class key
 };
 
+// An input sector after the integration by parts of Eq. 13 (qmc_ibp.cpp),
+// or unchanged when none of its exponents is below -1: exponents, U, F and
+// numerator factors as term lists ([terms][dim] exponents, [terms][n_inv]
+// coefficients), powers of U and F, and the coefficient series C(eps)
+// (eps^0 .. QMC_MAX_ORDERS-1, times the input sector's D).
+struct qmc_ibp_sec {
+    int origin = 0;                  // index of the input sector
+    int dim = 0;
+    bool ibp = false;                // the input sector had some a_j < -1
+    std::vector<double> a, b;
+    std::vector<uint8_t> eU, eF;
+    std::vector<double> cU, cF;
+    std::vector<std::vector<uint8_t>> eP;
+    std::vector<std::vector<double>> cP;
+    double u0 = 0, u1 = 0, f0 = 0, f1 = 0;
+    std::vector<std::complex<double>> C;
+};
+
+// Every sector of the problem expanded by Eq. 13 where needed, in the
+// documented order.  Returns QMC_OK or an error code with a message in err.
+int qmc_ibp_expand(const qmc_problem *pb, std::vector<qmc_ibp_sec> &out, char *err,
+                   size_t errlen);
+
 // One sector as planned: permuted exponents, term ranges, flop count.
 struct qmc_sec_host {
     int dim = 0, ks = 0, K = 0, deform = 0;
@@ -57,7 +83,11 @@ struct qmc_sec_host {
     int u0i = 0, f0i = 0;
     double lambda = 0.0;
     bool mono_log = false;       // some term needs exp(sum_j e_j ln t_j)
-    std::complex<double> D = 1.0;
+    int origin = 0;                  // input sector it comes from
+    int nf = 0;                      // numerator factors (Eq. 13)
+    int32_t pm[QMC_NFMAX][QMC_NMASK + 1] = {};
+    int32_t pm1[QMC_NFMAX][QMC_NMASK] = {}, pm2[QMC_NFMAX][QMC_NMASK] = {};
+    std::vector<std::complex<double>> C{1.0};   // coefficient series, eps^0 ..
     std::vector<int> term_nnz;   // non-zero exponents per term (U and F)
     std::vector<int> dterm_nnz;  // the same for the derivative terms
     double flops = 0.0;          // algorithmic flops per lattice point
@@ -76,6 +106,7 @@ struct qmc_plan {
     int kb = 1;                      // orders from eps^0 up: sec_hi + 1
     int kstride = 1;                 // order slots per group: kb + max_ks
     int max_ks = 0;
+    int n_input_sectors = 0;         // sectors given; secs holds them after Eq. 13
     std::vector<qmc_sec_host> secs;
     std::vector<uint32_t> texp;      // packed exponents of all U and F terms
     std::vector<double> tcoef_rows;  // [n_terms][n_inv]
@@ -97,6 +128,7 @@ constexpr int QMC_MAX_GRID = (int)(0xffffffffu / QMC_BLOCK);
 
 struct qmc_class {                   // items launched by one kernel instance
     int ks = 0, kb = 1, deform = 0, dm = 0;
+    int num = 0;                     // sectors with numerator factors (Eq. 13)
     int begin = 0, end = 0;
     int grid = 0;                    // work-groups (0: one per item)
     int ppl = 0;                     // lattice points per lane per item
@@ -157,7 +189,7 @@ int qmc_bind_impl(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t
                   const qmc_lattice *lat, const qmc_lattice *lat_per_sector,
                   const double *shifts, int32_t m, int ppl_override, int grid_override,
                   bool class_timing, qmc_job **out);
-std::string qmc_tune_key(const qmc_plan *plan, int ks, int dm, uint64_t n);
+std::string qmc_tune_key(const qmc_plan *plan, int ks, int dm, int num, uint64_t n);
 void qmc_job_release(qmc_job *job);
 int qmc_assemble(const qmc_plan *plan, int n_points, int m, const std::vector<uint64_t> &nsec,
                  const double *gsum, qmc_result *out);

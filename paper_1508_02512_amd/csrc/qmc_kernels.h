@@ -8,9 +8,10 @@
 // Real (Euclidean) integrand for sectors with `ks` poles carrying ks + kb
 // Laurent orders, evaluated in FP64 or FP32; one work-group per item in
 // [item_begin, item_end).  variant 0 is the build with the swept occupancy,
-// variant 1 the build with one wave per SIMD fewer (less spilling).
-hipError_t qmc_launch_real(int ks, int kb, bool fp32, int variant, const qmc_launch_args &args,
-                           int grid, hipStream_t stream);
+// variant 1 the build with one wave per SIMD fewer (less spilling).  num:
+// the sectors carry numerator factors (Eq. 13; variant 0 only).
+hipError_t qmc_launch_real(int ks, int kb, bool fp32, int variant, bool num,
+                           const qmc_launch_args &args, int grid, hipStream_t stream);
 
 // Complex integrand with contour deformation (Eq. 14) for sectors of
 // dimension <= dm (dm = qmc_cplx_dm(dim)); polynomial work in FP32 when
@@ -36,7 +37,8 @@ hipError_t qmc_launch_serve_accumulate(const double *partial, const int32_t *vio
                                        double *const *dst, const int32_t *gks, int n_groups,
                                        int kstride, int32_t *gviol, hipStream_t stream);
 // Serving: a request's sums [ns][m][kstride][4] combined over sectors per
-// shift and sector order: tot[m][n_orders][2].
+// shift and sector order, each sector's series times its coefficient series
+// D[ns][QMC_NCOEF][2]: tot[m][n_orders][2].
 hipError_t qmc_launch_serve_combine(const double *sums, const qmc_sec_dev *sec, const double *D,
                                     int ns, int m, int kstride, int n_orders, int sec_lo,
                                     double inv_n, double *tot, hipStream_t stream);

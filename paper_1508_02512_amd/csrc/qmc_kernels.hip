@@ -17,11 +17,19 @@ QMC_REAL_LAUNCHER(qmc_launch_real_f32)
 QMC_REAL_LAUNCHER(qmc_launch_real_lo_v1)
 QMC_REAL_LAUNCHER(qmc_launch_real_hi_v1)
 QMC_REAL_LAUNCHER(qmc_launch_real_f32_v1)
+QMC_REAL_LAUNCHER(qmc_launch_real_num_lo)
+QMC_REAL_LAUNCHER(qmc_launch_real_num_hi)
+QMC_REAL_LAUNCHER(qmc_launch_real_num_f32)
 
-hipError_t qmc_launch_real(int ks, int kb, bool fp32, int variant, const qmc_launch_args &args,
-                           int grid, hipStream_t stream)
+hipError_t qmc_launch_real(int ks, int kb, bool fp32, int variant, bool num,
+                           const qmc_launch_args &args, int grid, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
+    if (num) {   // one occupancy build: these classes are small
+        if (fp32) return qmc_launch_real_num_f32(ks, kb, args, grid, stream);
+        return ks <= 2 ? qmc_launch_real_num_lo(ks, kb, args, grid, stream)
+                       : qmc_launch_real_num_hi(ks, kb, args, grid, stream);
+    }
     if (variant == 1) {
         if (fp32) return qmc_launch_real_f32_v1(ks, kb, args, grid, stream);
         return ks <= 2 ? qmc_launch_real_lo_v1(ks, kb, args, grid, stream)
@@ -159,16 +167,21 @@ __global__ void qmc_serve_combine_k(const double *sums, const qmc_sec_dev *sec,
     const int k = tid / n_orders, j = tid % n_orders;
     double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
     for (int s = 0; s < ns; ++s) {
-        const int q = j + sec_lo + sec[s].ks;
-        if (q < 0 || q >= sec[s].K) continue;
-        const double *p = sums + (((size_t)s * m + k) * kstride + q) * 4;
-        const double vr = (p[0] + p[1]) * inv_n, vi = (p[2] + p[3]) * inv_n;
-        const double dr = D[2 * s], di = D[2 * s + 1];
-        double e;
-        two_sum(sr, dr * vr - di * vi, sr, e);
-        cr += e;
-        two_sum(si, dr * vi + di * vr, si, e);
-        ci += e;
+        // order j of the sector's series times C(eps): sum_e C_e v_{j-e}
+        for (int e = 0; e < QMC_NCOEF; ++e) {
+            const double dr = D[2 * (s * QMC_NCOEF + e)];
+            const double di = D[2 * (s * QMC_NCOEF + e) + 1];
+            if (dr == 0.0 && di == 0.0) continue;
+            const int q = j - e + sec_lo + sec[s].ks;
+            if (q < 0 || q >= sec[s].K) continue;
+            const double *p = sums + (((size_t)s * m + k) * kstride + q) * 4;
+            const double vr = (p[0] + p[1]) * inv_n, vi = (p[2] + p[3]) * inv_n;
+            double x;
+            two_sum(sr, dr * vr - di * vi, sr, x);
+            cr += x;
+            two_sum(si, dr * vi + di * vr, si, x);
+            ci += x;
+        }
     }
     tot[2 * tid] = sr + cr;
     tot[2 * tid + 1] = si + ci;

@@ -1,0 +1,10 @@
+// FP64 real integrand kernels with numerator factors (integration by parts,
+// Eq. 13) for sectors with at most two poles.
+#include "qmc_real.h"
+
+hipError_t qmc_launch_real_num_lo(int ks, int kb, const qmc_launch_args &args, int grid,
+                                  hipStream_t stream)
+{
+    QMC_REAL_CASES_LO(double, 0, true)
+    return hipErrorInvalidValue;
+}

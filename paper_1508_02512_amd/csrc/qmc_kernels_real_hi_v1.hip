@@ -5,6 +5,6 @@
 hipError_t qmc_launch_real_hi_v1(int ks, int kb, const qmc_launch_args &args, int grid,
                                  hipStream_t stream)
 {
-    QMC_REAL_CASES_HI(double, 1)
+    QMC_REAL_CASES_HI(double, 1, false)
     return hipErrorInvalidValue;
 }

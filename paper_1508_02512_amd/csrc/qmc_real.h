@@ -271,9 +271,12 @@ struct Accum {
 // X = u0 log U + f0 log F and B = u1 log U + f1 log F + LN, accumulated into
 //   g = sum_Y prod_{j not in Y} 1/(b_j eps) prod_{j in Y} t_j^-1 t_j^(b_j eps) h^[Y],
 // index o of g holding order o - KS.
-template <int KS, int K, typename T>
+//
+// With numerator factors (NUM, Eq. 13) h carries their product N as well:
+// H = exp(X) is multiplied by N in the union algebra before the series.
+template <int KS, int K, typename T, bool NUM>
 __device__ __forceinline__ void mobius_series(cptr<qmc_sec_dev> S, Point<KS, K, T> &P,
-                                              T (&g)[K])
+                                              const T (&SN)[1 << KS], T (&g)[K])
 {
     constexpr int N = 1 << KS;
 #pragma unroll
@@ -312,10 +315,41 @@ __device__ __forceinline__ void mobius_series(cptr<qmc_sec_dev> S, Point<KS, K, 
         // the accumulation starts when the whole exponential is done:
         // overlapping the two keeps both phases' temporaries live
         mobius::fence<N, T>(H, H[N - 1]);
+        if constexpr (NUM) {
+            T R[N];
+            mobius::mul<KS, KS, T>(H, SN, R);
+#pragma unroll
+            for (int Y = 0; Y < N; ++Y) H[Y] = R[Y];
+        }
     }
 #pragma unroll
     for (int o = 0; o < K; ++o) g[o] = 0;
     Accum<KS, K, 0, T>::run(S, P, B, H, g);
+}
+
+// Product of a sector's numerator factors (integration by parts, Eq. 13)
+// as Moebius coefficients over the pole subsets: each factor's terms are
+// grouped by pole mask like those of U, and the factors are multiplied in
+// the union algebra (no subtraction, so no cancellation).
+template <int KS, typename T>
+__device__ __forceinline__ void numerator(cptr<qmc_sec_dev> S, cptr<uint32_t> toff,
+                                          cptr<uint32_t> toff2, cptr<double> coef,
+                                          const char *colb, cptr<double> texpd, const T *lt,
+                                          int d, T (&SN)[1 << KS])
+{
+    constexpr int N = 1 << KS;
+#pragma unroll
+    for (int Y = 0; Y < N; ++Y) SN[Y] = T(Y == 0 ? 1 : 0);
+    for (int i = 0; i < S->nf; ++i) {
+        T SP[N], R[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+            SP[m] = poly_group<T>(S->pm[i][m], S->pm1[i][m], S->pm2[i][m], S->pm[i][m + 1],
+                                  toff, toff2, coef, colb, texpd, lt, d);
+        mobius::mul<KS, KS, T>(SN, SP, R);
+#pragma unroll
+        for (int Y = 0; Y < N; ++Y) SN[Y] = R[Y];
+    }
 }
 
 // ---- kernel -------------------------------------------------------------
@@ -347,7 +381,7 @@ constexpr int lds_state_slots()
     return n > 0 ? n : 1;
 }
 
-template <int KS, int K, typename T>
+template <int KS, int K, typename T, bool NUM>
 __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, const int item_id,
                                                    T *col, double *st)
 {
@@ -461,9 +495,12 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                     P.SF[m] = poly_group<T>(S->fm[m], S->fm1[m], S->fm2[m], S->fm[m + 1], toff,
                                             toff2, coef, colb, texpd, lt, d);
                 }
+                T SN[1 << KS];
+                if constexpr (NUM)
+                    numerator<KS, T>(S, toff, toff2, coef, colb, texpd, lt, d, SN);
                 T g[K];
                 if constexpr (use_mobius<T, KS>()) {
-                    mobius_series<KS, K, T>(S, P, g);
+                    mobius_series<KS, K, T, NUM>(S, P, SN, g);
                 } else {
                     // subset sums: the value at the corner where the poles in X are 0
 #pragma unroll
@@ -475,6 +512,10 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                                 P.SF[Y] += P.SF[Y ^ (1 << i)];
                             }
                     Tree<KS, 0, KS, K, T>::run(S, P, g);
+                    if constexpr (NUM) {
+#pragma unroll
+                        for (int q = 0; q < K; ++q) g[q] *= SN[0];
+                    }
                 }
                 // a term that is not finite (U or F not positive at a
                 // corner, or an overflow) is counted, not summed
@@ -546,7 +587,7 @@ constexpr int min_waves()
     return V == 0 ? base : (base > 1 ? base - 1 : 1);
 }
 
-template <int KS, int K, typename T, int V>
+template <int KS, int K, typename T, int V, bool NUM>
 __global__ __launch_bounds__(QMC_BLOCK)
 __attribute__((amdgpu_waves_per_eu(min_waves<KS, T, V>(), 8))) void qmc_eval_real(qmc_launch_args A)
 {
@@ -556,25 +597,25 @@ __attribute__((amdgpu_waves_per_eu(min_waves<KS, T, V>(), 8))) void qmc_eval_rea
     __shared__ double st[lds_state_slots<KS, K, T>() * QMC_BLOCK];
     pw[(QMC_PROG_SLOTS - 1) * QMC_BLOCK + threadIdx.x] = T(1);
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
-        qmc_eval_real_item<KS, K, T>(A, item, pw + threadIdx.x, st + threadIdx.x);
+        qmc_eval_real_item<KS, K, T, NUM>(A, item, pw + threadIdx.x, st + threadIdx.x);
         __syncthreads();
     }
 }
 
 } // namespace qmc_real
 
-#define QMC_REAL_CASE(KS, KB, T, V)                                                 \
-    if (ks == KS && kb == KB) {                                                     \
-        hipLaunchKernelGGL((qmc_real::qmc_eval_real<KS, KS + KB, T, V>), dim3(grid), \
-                           dim3(QMC_BLOCK), 0, stream, args);                       \
-        return hipGetLastError();                                                   \
+#define QMC_REAL_CASE(KS, KB, T, V, NUM)                                               \
+    if (ks == KS && kb == KB) {                                                        \
+        hipLaunchKernelGGL((qmc_real::qmc_eval_real<KS, KS + KB, T, V, NUM>), dim3(grid), \
+                           dim3(QMC_BLOCK), 0, stream, args);                          \
+        return hipGetLastError();                                                      \
     }
 
-#define QMC_REAL_CASES_LO(T, V)                                                     \
-    QMC_REAL_CASE(0, 1, T, V) QMC_REAL_CASE(0, 2, T, V) QMC_REAL_CASE(0, 3, T, V)  \
-    QMC_REAL_CASE(1, 1, T, V) QMC_REAL_CASE(1, 2, T, V) QMC_REAL_CASE(1, 3, T, V)  \
-    QMC_REAL_CASE(2, 1, T, V) QMC_REAL_CASE(2, 2, T, V) QMC_REAL_CASE(2, 3, T, V)
+#define QMC_REAL_CASES_LO(T, V, NUM)                                                           \
+    QMC_REAL_CASE(0, 1, T, V, NUM) QMC_REAL_CASE(0, 2, T, V, NUM) QMC_REAL_CASE(0, 3, T, V, NUM) \
+    QMC_REAL_CASE(1, 1, T, V, NUM) QMC_REAL_CASE(1, 2, T, V, NUM) QMC_REAL_CASE(1, 3, T, V, NUM) \
+    QMC_REAL_CASE(2, 1, T, V, NUM) QMC_REAL_CASE(2, 2, T, V, NUM) QMC_REAL_CASE(2, 3, T, V, NUM)
 
-#define QMC_REAL_CASES_HI(T, V)                                                     \
-    QMC_REAL_CASE(3, 1, T, V) QMC_REAL_CASE(3, 2, T, V) QMC_REAL_CASE(3, 3, T, V)  \
-    QMC_REAL_CASE(4, 1, T, V) QMC_REAL_CASE(4, 2, T, V) QMC_REAL_CASE(4, 3, T, V)
+#define QMC_REAL_CASES_HI(T, V, NUM)                                                           \
+    QMC_REAL_CASE(3, 1, T, V, NUM) QMC_REAL_CASE(3, 2, T, V, NUM) QMC_REAL_CASE(3, 3, T, V, NUM) \
+    QMC_REAL_CASE(4, 1, T, V, NUM) QMC_REAL_CASE(4, 2, T, V, NUM) QMC_REAL_CASE(4, 3, T, V, NUM)

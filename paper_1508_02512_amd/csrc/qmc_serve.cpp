@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -304,12 +305,14 @@ int admit_device(qmc_serve_state *S, Request *r)
         if (!rc) rc = dev_alloc(S, pp.dcoef, (size_t)slots * std::max<size_t>(P->dexp.size(), 1) * 8);
         if (!rc) rc = dev_alloc(S, pp.lam, (size_t)slots * ns * 8);
         if (!rc) rc = dev_alloc(S, pp.lat, (size_t)slots * ns * sizeof(qmc_lat_dev));
-        if (!rc) rc = dev_alloc(S, pp.D, (size_t)ns * 16);
-        std::vector<double> D(2 * ns);
-        for (int s = 0; s < ns; ++s) {
-            D[2 * s] = P->secs[s].D.real();
-            D[2 * s + 1] = P->secs[s].D.imag();
-        }
+        // coefficient series C(eps) of every sector: [ns][QMC_MAX_ORDERS][2]
+        if (!rc) rc = dev_alloc(S, pp.D, (size_t)ns * QMC_MAX_ORDERS * 16);
+        std::vector<double> D((size_t)2 * ns * QMC_MAX_ORDERS, 0.0);
+        for (int s = 0; s < ns; ++s)
+            for (size_t e = 0; e < P->secs[s].C.size() && e < (size_t)QMC_MAX_ORDERS; ++e) {
+                D[2 * ((size_t)s * QMC_MAX_ORDERS + e)] = P->secs[s].C[e].real();
+                D[2 * ((size_t)s * QMC_MAX_ORDERS + e) + 1] = P->secs[s].C[e].imag();
+            }
         if (!rc && hipMemcpyAsync(pp.D.p, D.data(), D.size() * 8, hipMemcpyHostToDevice, st) !=
                        hipSuccess)
             rc = QMC_EDEVICE;
@@ -446,19 +449,21 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act, std::vector<Reques
     std::vector<Launch> launches;
     for (const qmc_plan *P : plans) {
         const int ns = (int)P->secs.size();
-        std::vector<std::pair<int, int>> keys;
+        // (poles, kernel width or 0, numerator factors or not)
+        std::vector<std::array<int, 3>> keys;
         for (const Win &w : wins) {
             if (w.r->plan != P) continue;
             for (int s = 0; s < ns; ++s) {
-                std::pair<int, int> key{P->secs[s].ks, w.r->dm[s]};
+                std::array<int, 3> key{P->secs[s].ks, w.r->dm[s], P->secs[s].nf > 0 ? 1 : 0};
                 if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
             }
         }
         std::sort(keys.begin(), keys.end());
         for (const auto &key : keys) {
             qmc_class c{};
-            c.ks = key.first;
-            c.dm = key.second;
+            c.ks = key[0];
+            c.dm = key[1];
+            c.num = key[2];
             c.deform = c.dm != 0;
             c.kb = P->kb;
             c.begin = (int)items.size();
@@ -469,7 +474,9 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act, std::vector<Reques
                 const uint64_t g0 = w.begin / ipg, g1 = (w.end - 1) / ipg;
                 for (uint64_t g = g0; g <= g1; ++g) {
                     const int s = (int)(g / r->m), k = (int)(g % r->m);
-                    if (P->secs[s].ks != c.ks || r->dm[s] != c.dm) continue;
+                    if (P->secs[s].ks != c.ks || r->dm[s] != c.dm ||
+                        (P->secs[s].nf > 0 ? 1 : 0) != c.num)
+                        continue;
                     gbeg.push_back((int32_t)items.size());
                     const uint64_t i0 = std::max(w.begin, g * ipg), i1 = std::min(w.end, (g + 1) * ipg);
                     for (uint64_t i = i0; i < i1; ++i) {

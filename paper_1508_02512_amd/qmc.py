@@ -20,9 +20,13 @@ QMC_OK, QMC_PENDING = 0, 1
 ERRORS = {-1: "QMC_EINVAL", -2: "QMC_EUNREGULATED", -3: "QMC_EUNSUPPORTED",
           -4: "QMC_ENOMEM", -5: "QMC_EBUDGET", -6: "QMC_EDEFORM",
           -7: "QMC_ENOTCONVERGED", -8: "QMC_EDEVICE", -9: "QMC_ECANCELLED"}
+(QMC_EINVAL, QMC_EUNREGULATED, QMC_EUNSUPPORTED, QMC_ENOMEM, QMC_EBUDGET, QMC_EDEFORM,
+ QMC_ENOTCONVERGED, QMC_EDEVICE, QMC_ECANCELLED) = range(-1, -10, -1)
 QMC_FP64, QMC_FP32_EVAL = 0, 1
 QMC_MATH_LN, QMC_MATH_LN1P, QMC_MATH_EXP, QMC_MATH_EXPM1, QMC_MATH_RCP = 0, 1, 2, 3, 4
 QMC_MAX_DIM = 8
+QMC_MAX_ORDERS = 8
+QMC_MAX_FACTORS = 4
 QMC_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 P = C.POINTER
@@ -62,7 +66,14 @@ class qmc_plan_info(C.Structure):
     _fields_ = [("n_sectors", C.c_int32), ("n_inv", C.c_int32), ("sec_lo", C.c_int32),
                 ("sec_orders", C.c_int32), ("eps_lo", C.c_int32), ("eps_hi", C.c_int32),
                 ("max_poles", C.c_int32), ("deform", C.c_int32),
-                ("flops_per_point", C.c_double)]
+                ("flops_per_point", C.c_double), ("n_input_sectors", C.c_int32),
+                ("max_factors", C.c_int32)]
+
+
+class qmc_sector_info(C.Structure):
+    _fields_ = [("origin", C.c_int32), ("dim", C.c_int32), ("poles", C.c_int32),
+                ("factors", C.c_int32), ("u_exp", C.c_double * 2), ("f_exp", C.c_double * 2),
+                ("coef", (C.c_double * 2) * QMC_MAX_ORDERS)]
 
 
 class qmc_result(C.Structure):
@@ -101,6 +112,7 @@ _SIGS = {
                                    P(C.c_void_p)]),
     "qmc_plan_free": (None, [C.c_void_p]),
     "qmc_plan_get_info": (C.c_int, [C.c_void_p, P(qmc_plan_info)]),
+    "qmc_plan_sector_info": (C.c_int, [C.c_void_p, C.c_int32, P(qmc_sector_info)]),
     "qmc_integrate": (C.c_int, [C.c_void_p, C.c_void_p, P(C.c_double), C.c_int32,
                                 P(qmc_lattice), P(qmc_lattice), P(C.c_double), C.c_int32,
                                 P(qmc_result)]),
@@ -239,8 +251,11 @@ class Plan:
         prob.eps_pref_lo = pref_lo
         prob.n_pref = len(pref)
         prob.prefactor = _dptr(self.pref_arr)
-        # lowest order of the result: -max poles + prefactor's lowest order
-        max_poles = max(int(np.sum(s["a"] == -1.0)) for s in sectors)
+        # lowest order of the result: -max poles + prefactor's lowest order;
+        # integration by parts (Eq. 13) can turn an integer a_j < -1 into a
+        # pole, so every integer a_j <= -1 counts
+        max_poles = max(int(np.sum((s["a"] <= -1.0) & (s["a"] == np.floor(s["a"]))))
+                        for s in sectors)
         prob.eps_lo = -max_poles + pref_lo
         opts = qmc_plan_opts(precision, korobov_r, float(lam), points_per_lane)
         self.h = C.c_void_p()
@@ -248,7 +263,18 @@ class Plan:
                                          C.byref(self.h)))
         self.info = qmc_plan_info()
         ctx.check(lib().qmc_plan_get_info(self.h, C.byref(self.info)))
-        self.n_sectors = ns
+        self.n_input_sectors = ns
+        self.n_sectors = self.info.n_sectors      # after Eq. 13
+
+    def sector_info(self, s):
+        """Planned sector s: origin, dim, poles, factors, u, f and the
+        coefficient series C(eps) (complex array, eps^0 ..)."""
+        out = qmc_sector_info()
+        self.ctx.check(lib().qmc_plan_sector_info(self.h, int(s), C.byref(out)))
+        return {"origin": out.origin, "dim": out.dim, "poles": out.poles,
+                "factors": out.factors, "u": tuple(out.u_exp), "f": tuple(out.f_exp),
+                "C": np.array([complex(out.coef[k][0], out.coef[k][1])
+                               for k in range(QMC_MAX_ORDERS)])}
 
     def close(self):
         if self.h:

@@ -3,6 +3,7 @@ oracle on identical lattice and shifts, compare sector by sector."""
 
 import numpy as np
 
+from oracle import ibp
 from oracle import qmc as oq
 from oracle.decompose import decompose as odec
 from oracle.geometric import decompose as ogeo
@@ -25,7 +26,17 @@ def ctx():
 
 
 def oracle_sectors(name, strategy="iterated"):
-    return (ogeo if strategy == "geometric" else odec)(PROBLEMS[name])
+    """The oracle's sectors of a problem, after its own integration by parts
+    (Eq. 13) where some a_j < -1: one to one with the planned sectors."""
+    secs, info = (ogeo if strategy == "geometric" else odec)(PROBLEMS[name])
+    if ibp.needs_ibp(secs):
+        secs = ibp.expand(secs, info)
+    return secs, info
+
+
+def sector_coef(s):
+    """A sector's constant D, or its coefficient series C(eps) after Eq. 13."""
+    return s["C"] if "C" in s else float(s.get("D", 1))
 
 
 def gpu_plan(name, eps_hi=0, lam=0.0, r=2, ppl=0, precision=qmc.QMC_FP64,
@@ -100,10 +111,11 @@ def oracle_assembled(name, kin, n, z, shifts, eps_hi=0, lam=0.0, r=2, strategy="
                                        sec_lo, K, quad=ns.nJ >= quad_from)
         per.append(sums)
         per_abs.append((abss[..., 0] + abss[..., 1]).astype(complex))
-    D = [float(s.get("D", 1)) for s in osecs]
+    D = [sector_coef(s) for s in osecs]
+    Dabs = [{k: abs(v) for k, v in d.items()} if isinstance(d, dict) else abs(d) for d in D]
     eps_lo = sec_lo + pref_lo
     res = oq.assemble(per, D, pref, pref_lo, sec_lo, n, eps_lo, eps_hi)
-    absres = oq.assemble(per_abs, [abs(d) for d in D], {k: abs(v) for k, v in pref.items()},
+    absres = oq.assemble(per_abs, Dabs, {k: abs(v) for k, v in pref.items()},
                          pref_lo, sec_lo, n, eps_lo, eps_hi)
     res["scale"] = np.max(np.abs(absres["per_shift"]), axis=0)
     return res

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 STRUCTS = ("qmc_poly", "qmc_sector", "qmc_problem", "qmc_plan_opts", "qmc_lattice",
            "qmc_coeff", "qmc_plan_info", "qmc_result", "qmc_tune_choice", "qmc_class_stat",
-           "qmc_request")
+           "qmc_request", "qmc_sector_info")
 
 
 def test_binding_structs_match_header_layout(tmp_path):
@@ -59,6 +59,13 @@ def test_binding_structs_match_header_layout(tmp_path):
         assert int(got[name]) == ctypes.sizeof(T), name
         for f, _ in T._fields_:
             assert int(got[f"{name}.{f}"]) == getattr(T, f).offset, f"{name}.{f}"
+
+
+def test_limits_match_binding():
+    text = open(os.path.join(ROOT, "include", "qmc.h")).read()
+    for name in ("QMC_MAX_DIM", "QMC_MAX_ORDERS", "QMC_MAX_FACTORS"):
+        m = re.search(rf"#define {name} (\d+)", text)
+        assert m and int(m.group(1)) == getattr(qmc, name), name
 
 
 def test_noalloc_scratch_size_matches_binding():

@@ -1,0 +1,144 @@
+"""GPU path of the integration by parts (Section II, Eq. 13) for sector
+exponents a_j < -1 (dotted propagators): the planner's expansion against
+the oracle's, sector sums per (sector, shift, order) against the oracle at
+1e-12 of sum |w g|, the assembled result and Eq. 20 errors against the
+oracle's, whole results against Gamma-function closed forms, serving, and
+the refusals."""
+
+import numpy as np
+import pytest
+
+from gpu_util import (assert_assembly_matches, compare_sectors, ctx, gpu_plan,
+                      oracle_assembled, oracle_sectors)
+from oracle.decompose import decompose as odec
+from paper_1508_02512_amd import frontend as fe
+from paper_1508_02512_amd import qmc
+from seeded_inputs.lattice import embedded_lattice, lattice
+from seeded_inputs.problems import PROBLEMS, Problem, _P
+from seeded_inputs.rng import shift_table
+from test_oracle_ibp import _bubble, _laurent, _sunset
+
+pytestmark = pytest.mark.gpu
+
+# (problem, kinematic point, eps_hi)
+DOTTED = [
+    ("bubble_dot", {"s": -3.0}, 1),
+    ("bubble_dot23", {"s": -0.4}, 1),
+    ("bubble_dot14", {"s": -3.0}, 1),
+    ("bubble_massive_dot", {"s": -2.0, "msq": 1.5}, 1),
+    ("sunset_dot", {"s": -2.0}, 0),
+    ("sunset_dot114", {"s": -2.0}, 0),
+    ("sunset_dot123", {"s": -2.0}, 0),
+    ("triangle_offshell_dot", {"p1sq": -1.0, "p2sq": -2.0, "p3sq": -3.0}, 0),
+    ("box_dot", {"s": -3.0, "t": -2.0}, 0),
+]
+
+
+@pytest.mark.parametrize("name,kin,eps_hi", DOTTED)
+def test_planned_sectors_match_oracle_expansion(name, kin, eps_hi):
+    print(f"ibp plan: {name}", flush=True)
+    plan, _ = gpu_plan(name, eps_hi)
+    osecs, _ = oracle_sectors(name)
+    assert plan.n_input_sectors == len(odec(PROBLEMS[name])[0])
+    assert plan.n_sectors == len(osecs) > plan.n_input_sectors - 1
+    for s, o in enumerate(osecs):
+        si = plan.sector_info(s)
+        assert si["origin"] == o["origin"], s
+        assert si["dim"] == len(o["a"]), s
+        assert si["poles"] == sum(1 for a in o["a"] if a == -1), s
+        assert si["factors"] == len(o["P"]), s
+        assert si["u"] == tuple(float(x) for x in o["u"]), s
+        assert si["f"] == tuple(float(x) for x in o["f"]), s
+        want = np.array([float(o["C"].get(k, 0)) for k in range(qmc.QMC_MAX_ORDERS)])
+        assert np.allclose(si["C"].real, want, rtol=1e-14, atol=1e-14), (s, si["C"], want)
+        assert np.all(si["C"].imag == 0.0)
+    plan.close()
+
+
+@pytest.mark.parametrize("name,kin,eps_hi", DOTTED)
+def test_sector_sums_match_oracle(name, kin, eps_hi):
+    """Every planned sector (numerator factors in the kernel, boundary
+    sectors on their dummy variable) against the oracle on the same
+    lattice and shifts: 3 shifts, n = 10007 (ragged last tile)."""
+    print(f"ibp parity: {name}", flush=True)
+    compare_sectors(name, kin, 10007, 3, eps_hi=eps_hi)
+
+
+def test_sector_sums_many_tiles_and_persistent_points_per_lane():
+    print("ibp parity: box_dot, ppl 3", flush=True)
+    compare_sectors("box_dot", {"s": -3.0, "t": -2.0}, 100003, 2, ppl=3)
+
+
+@pytest.mark.parametrize("name,kin,eps_hi", [DOTTED[3], DOTTED[6], DOTTED[8]])
+def test_assembly_and_errors_match_oracle(name, kin, eps_hi):
+    """Laurent assembly with the sectors' coefficient series C(eps), and
+    the Eq. 20 errors, against the oracle's."""
+    print(f"ibp assembly: {name}", flush=True)
+    plan, info = gpu_plan(name, eps_hi)
+    n, m = 4099, 5
+    z = lattice(n)
+    shifts = shift_table(3, m, 8)
+    res = plan.integrate(fe.kin_vector(info, kin), (n, z), shifts)
+    ora = oracle_assembled(name, kin, n, z, shifts, eps_hi=eps_hi)
+    lo = ora["orders"][0]
+    k = list(res["orders"]).index(lo)
+    gpu = {key: (np.asarray(res[key])[:, k:] if key != "orders" else list(res["orders"])[k:])
+           for key in ("mean", "err_re", "err_im", "orders")}
+    # orders below the oracle's lowest (a bound taken before Eq. 13) are 0
+    assert np.all(np.asarray(res["mean"])[:, :k] == 0)
+    assert_assembly_matches(gpu, ora)
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [qmc.QMC_FP64, qmc.QMC_FP32_EVAL])
+def test_whole_results_against_closed_forms(precision):
+    """Whole GPU results within 6 standard errors of the closed forms
+    (FP32 evaluation: also within 1e-5 relative)."""
+    cases = [("bubble_dot14", {"s": -3.0}, 1, _laurent(_bubble(1, 4, -3.0), -1, 1)),
+             ("sunset_dot114", {"s": -2.0}, 0, _laurent(_sunset(1, 1, 4, -2.0), -2, 0)),
+             ("sunset_dot123", {"s": -2.0}, 0, _laurent(_sunset(1, 2, 3, -2.0), -2, 0))]
+    n, m = 100003, 8
+    for name, kin, eps_hi, exact in cases:
+        print(f"ibp closed form: {name} precision {precision}", flush=True)
+        plan, info = gpu_plan(name, eps_hi, precision=precision)
+        res = plan.integrate(fe.kin_vector(info, kin), (n, lattice(n)), shift_table(0, m, 8))
+        for p, want in exact.items():
+            i = list(res["orders"]).index(p)
+            got, err = res["mean"][0][i], res["err_re"][0][i]
+            tol = 6 * err + 1e-12 * max(1.0, abs(want))
+            if precision == qmc.QMC_FP32_EVAL:
+                tol += 1e-5 * max(1.0, abs(want))
+            assert abs(got.real - want.real) <= tol, (name, p, got, want, err)
+        plan.close()
+
+
+def test_served_request_with_integration_by_parts():
+    """A served request on a plan expanded by Eq. 13: converges, and its
+    result equals one pass of qmc_integrate over the same 2^k points."""
+    print("ibp serve: sunset_dot123", flush=True)
+    plan, info = gpu_plan("sunset_dot123")
+    kin = fe.kin_vector(info, {"s": -2.0})
+    z = embedded_lattice()
+    r = qmc.submit(plan, kin, 1e-9, 1 << 10, 1 << 20, 8, 5, z).wait(120)
+    assert r["rc"] == 0
+    ref = plan.integrate(kin, (r["n_final"], z), shift_table(5, 8, 8))
+    assert np.allclose(r["mean"], ref["mean"], rtol=1e-12, atol=1e-14)
+    exact = _laurent(_sunset(1, 2, 3, -2.0), -2, 0)
+    for p, want in exact.items():
+        i = list(r["orders"]).index(p)
+        assert abs(r["mean"][0][i].real - want.real) <= 6 * r["err_re"][0][i] + 1e-12
+    plan.close()
+
+
+def test_refusals():
+    # Eq. 13 with contour deformation is not supported
+    with pytest.raises(qmc.QMCError) as e:
+        gpu_plan("box_dot", lam=0.5)
+    assert e.value.code == qmc.QMC_EUNSUPPORTED and "Euclidean" in str(e.value)
+    # powers (1, 1, 5) need five numerator factors in some sector
+    prob = Problem("sunset_115", 2, ("p",), ("s",), {("p", "p"): {"s": "1"}},
+                   (_P([1, 0]), _P([0, 1]), _P([1, 1], {"p": -1}, power=5)))
+    secs, info = fe.decompose(prob)
+    with pytest.raises(qmc.QMCError) as e:
+        ctx().plan(fe.sector_arrays(secs, info), info, 0, fe.prefactor_series(info, 12))
+    assert e.value.code == qmc.QMC_EUNSUPPORTED and "numerator factors" in str(e.value)

@@ -131,12 +131,16 @@ def test_invalid_inputs_raise():
     with pytest.raises(qmc.QMCError) as e:
         ctx().plan(bad, info, 0, fe.prefactor_series(info, 8))
     assert e.value.code == -2
+    # a = -2 goes through the integration by parts of Eq. 13, which ends at
+    # a = -1: with b = 0 that pole is not regulated either
     bad = [dict(s) for s in arrs]
     bad[0]["a"] = bad[0]["a"].copy()
+    bad[0]["b"] = bad[0]["b"].copy()
     bad[0]["a"][j] = -2.0
+    bad[0]["b"][j] = 0.0
     with pytest.raises(qmc.QMCError) as e:
         ctx().plan(bad, info, 0, fe.prefactor_series(info, 8))
-    assert e.value.code == -3
+    assert e.value.code == -2
 
 
 def test_degenerate_and_oversized_inputs_raise():
