@@ -189,7 +189,8 @@ void qmc_destroy(qmc_ctx *ctx);
 int qmc_set_stream(qmc_ctx *ctx, void *hip_stream);
 const char *qmc_last_error(qmc_ctx *ctx);
 
-/* Validate the sectors, apply Eq. 13 where some a_j < -1, permute each
+/* Plan the sectors of Eq. 9 (Section II): validate them, apply Eq. 13
+ * where some a_j < -1, permute each
  * sector's variables so the subtracted ones come first, sort polynomial
  * terms by which of those they contain, derive dF and d2F tables when
  * lambda > 0, and upload the tables.  Everything sized "per sector" below
@@ -204,7 +205,12 @@ int qmc_plan_sector_info(const qmc_plan *plan, int32_t s, qmc_sector_info *out);
 
 /* Integrate at n_points kinematic points kin[n_points][n_inv] with the
  * lattice `lat` (or lat_per_sector[n_sectors] if not NULL) and the shifts
- * shifts[m][QMC_MAX_DIM] (m >= 2).  Blocks until the result is ready. */
+ * shifts[m][QMC_MAX_DIM] (m >= 2): the shifted rank-1 lattice sums of
+ * Section III (Eqs. 17-18, Korobov periodiser Eq. 21 at order korobov_r)
+ * of every sector's subtracted integrand (Eqs. 9-11; Eq. 14 when
+ * lambda > 0), combined per shift into the Laurent coefficients and
+ * reduced to mean and error (Eqs. 19-20).  Blocks until the result is
+ * ready. */
 int qmc_integrate(qmc_ctx *ctx, const qmc_plan *plan, const double *kin,
                   int32_t n_points, const qmc_lattice *lat,
                   const qmc_lattice *lat_per_sector, const double *shifts,
