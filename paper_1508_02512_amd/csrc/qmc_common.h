@@ -191,12 +191,23 @@ __device__ __forceinline__ T prod4(uint32_t w, const T *col)
     return (a * b) * (c * e);
 }
 
+// A program word copied into a vector register: the slots are then decoded
+// on the vector unit.  The deformed kernel, which reads its derivative
+// terms this way, is bound by its scalar unit (shared by the CU's four
+// SIMDs) while the vector units idle about half the time.
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t w)
+{
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(w));
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T tmono_lds(cptr<uint32_t> w, const T *col)
 {
     const uint32_t w0 = w[0];
-    T v = prod4<T>(w0, col);
-    if (w0 >> 30 & 1u) v *= prod4<T>(w[1], col);
+    T v = prod4<T>(to_vgpr(w0), col);
+    if (w0 >> 30 & 1u) v *= prod4<T>(to_vgpr(w[1]), col);
     return v;
 }
 
