@@ -293,6 +293,13 @@ typedef struct {
 
 int qmc_job_set_graph(qmc_job *job, int enable);
 
+/* Run every kernel class of a bound job with occupancy build `variant`
+ * (0 or 1, as qmc_tune_choice.occupancy_variant) instead of the one the
+ * bind chose; a captured graph is dropped and captured again on the next
+ * run.  Both builds compute the same sums (to rounding).  QMC_EINVAL for
+ * another variant or while the job is running. */
+int qmc_job_set_variant(qmc_job *job, int32_t variant);
+
 /* Per-kernel accounting of a bound job.  Each class of work items (poles,
  * complex width) is one kernel launch per qmc_run.  qmc_job_set_profiling
  * with enable != 0 records a HIP event pair around every class launch of

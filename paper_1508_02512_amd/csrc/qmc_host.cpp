@@ -1290,6 +1290,20 @@ extern "C" int qmc_job_set_graph(qmc_job *job, int enable)
     return QMC_OK;
 }
 
+extern "C" int qmc_job_set_variant(qmc_job *job, int32_t variant)
+{
+    if (!job) return QMC_EINVAL;
+    if (variant != 0 && variant != 1)
+        return set_err(job->ctx, QMC_EINVAL, "occupancy variant %d is not 0 or 1", variant);
+    if (job->launched) return set_err(job->ctx, QMC_EINVAL, "job is running");
+    for (qmc_class &c : job->classes) c.variant = variant;
+    if (job->graph) {
+        (void)hipGraphExecDestroy(job->graph);
+        job->graph = nullptr;
+    }
+    return QMC_OK;
+}
+
 extern "C" int qmc_job_set_profiling(qmc_job *job, int enable)
 {
     if (!job) return QMC_EINVAL;

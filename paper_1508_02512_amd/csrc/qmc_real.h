@@ -224,11 +224,19 @@ struct Tree<0, XB, KS, K, T> {
 // vanishes like prod_{j in Y} t_j, so every partial product stays of the
 // size of the result, while C(Y) alone can exceed the float range (four
 // poles at t_j ~ 1e-10).
-template <int KS, int K, int Q, typename T>
+//
+// With PRE (FP64 builds with registers to spare) C(Y) and L(Y) are formed
+// once per point, by subset products and sums, instead of at every order.
+template <int KS, typename T>
+struct SubsetConsts {
+    T C[1 << KS], L[1 << KS];
+};
+
+template <int KS, int K, int Q, typename T, bool PRE>
 struct Accum {
     static __device__ __forceinline__ void run(cptr<qmc_sec_dev> S, const Point<KS, K, T> &P,
                                                const T (&B)[1 << KS], T (&H)[1 << KS],
-                                               T (&g)[K])
+                                               T (&g)[K], const SubsetConsts<KS, T> &SC)
     {
         constexpr int N = 1 << KS;
 #pragma unroll
@@ -236,13 +244,18 @@ struct Accum {
             const int pc = __builtin_popcount(Y);
             if (Q + pc >= K) continue;
             T e = H[Y], L = 0;
+            if constexpr (PRE) {
+                e *= SC.C[Y];
+                L = SC.L[Y];
+            } else {
 #pragma unroll
-            for (int j = 0; j < KS; ++j) {
-                if (Y >> j & 1) {
-                    e *= P.invt[j];
-                    L = fma(T(S->b[j]), P.lt[j], L);
-                } else {
-                    e *= T(S->inv_b[j]);
+                for (int j = 0; j < KS; ++j) {
+                    if (Y >> j & 1) {
+                        e *= P.invt[j];
+                        L = fma(T(S->b[j]), P.lt[j], L);
+                    } else {
+                        e *= T(S->inv_b[j]);
+                    }
                 }
             }
 #pragma unroll
@@ -261,7 +274,7 @@ struct Accum {
             mobius::fence<N, T>(H, g[K - 1]);
             mobius::mul_inplace<KS, MAXPC, T>(H, B, T(1) / T(Q + 1));
             mobius::fence<N, T>(H, H[0]);
-            Accum<KS, K, Q + 1, T>::run(S, P, B, H, g);
+            Accum<KS, K, Q + 1, T, PRE>::run(S, P, B, H, g, SC);
         }
     }
 };
@@ -274,7 +287,7 @@ struct Accum {
 //
 // With numerator factors (NUM, Eq. 13) h carries their product N as well:
 // H = exp(X) is multiplied by N in the union algebra before the series.
-template <int KS, int K, typename T, bool NUM>
+template <int KS, int K, typename T, bool NUM, bool PRE>
 __device__ __forceinline__ void mobius_series(cptr<qmc_sec_dev> S, Point<KS, K, T> &P,
                                               const T (&SN)[1 << KS], T (&g)[K])
 {
@@ -322,9 +335,26 @@ __device__ __forceinline__ void mobius_series(cptr<qmc_sec_dev> S, Point<KS, K, 
             for (int Y = 0; Y < N; ++Y) H[Y] = R[Y];
         }
     }
+    SubsetConsts<KS, T> SC;
+    if constexpr (PRE) {
+        // C(Y u {j}) = C(Y) b_j / t_j and L(Y u {j}) = L(Y) + b_j ln t_j
+        SC.C[0] = T(1);
+#pragma unroll
+        for (int j = 0; j < KS; ++j) SC.C[0] *= T(S->inv_b[j]);
+        SC.L[0] = T(0);
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const T cj = T(S->b[j]) * P.invt[j], lj = T(S->b[j]) * P.lt[j];
+#pragma unroll
+            for (int Y = 0; Y < (1 << j); ++Y) {
+                SC.C[Y | (1 << j)] = SC.C[Y] * cj;
+                SC.L[Y | (1 << j)] = SC.L[Y] + lj;
+            }
+        }
+    }
 #pragma unroll
     for (int o = 0; o < K; ++o) g[o] = 0;
-    Accum<KS, K, 0, T>::run(S, P, B, H, g);
+    Accum<KS, K, 0, T, PRE>::run(S, P, B, H, g, SC);
 }
 
 // Product of a sector's numerator factors (integration by parts, Eq. 13)
@@ -381,7 +411,7 @@ constexpr int lds_state_slots()
     return n > 0 ? n : 1;
 }
 
-template <int KS, int K, typename T, bool NUM>
+template <int KS, int K, typename T, bool NUM, bool PRE>
 __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, const int item_id,
                                                    T *col, double *st)
 {
@@ -500,7 +530,7 @@ __device__ __forceinline__ void qmc_eval_real_item(const qmc_launch_args &A, con
                     numerator<KS, T>(S, toff, toff2, coef, colb, texpd, lt, d, SN);
                 T g[K];
                 if constexpr (use_mobius<T, KS>()) {
-                    mobius_series<KS, K, T, NUM>(S, P, SN, g);
+                    mobius_series<KS, K, T, NUM, PRE>(S, P, SN, g);
                 } else {
                     // subset sums: the value at the corner where the poles in X are 0
 #pragma unroll
@@ -597,7 +627,10 @@ __attribute__((amdgpu_waves_per_eu(min_waves<KS, T, V>(), 8))) void qmc_eval_rea
     __shared__ double st[lds_state_slots<KS, K, T>() * QMC_BLOCK];
     pw[(QMC_PROG_SLOTS - 1) * QMC_BLOCK + threadIdx.x] = T(1);
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
-        qmc_eval_real_item<KS, K, T, NUM>(A, item, pw + threadIdx.x, st + threadIdx.x);
+        // the one-wave-fewer FP64 builds of three and four poles have
+        // registers to spare for the subset constants
+        constexpr bool PRE = sizeof(T) == 8 && V == 1 && KS >= 3;
+        qmc_eval_real_item<KS, K, T, NUM, PRE>(A, item, pw + threadIdx.x, st + threadIdx.x);
         __syncthreads();
     }
 }

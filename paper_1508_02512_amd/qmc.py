@@ -129,6 +129,7 @@ _SIGS = {
     "qmc_fetch": (C.c_int, [C.c_void_p, P(qmc_result)]),
     "qmc_job_free": (None, [C.c_void_p]),
     "qmc_job_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
+    "qmc_job_set_variant": (C.c_int, [C.c_void_p, C.c_int32]),
     "qmc_job_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
     "qmc_job_class_stats": (C.c_int, [C.c_void_p, P(qmc_class_stat), C.c_int32,
                                       P(C.c_int32)]),
@@ -437,6 +438,10 @@ class Job:
 
     def use_graph(self, enable=True):
         self.plan.ctx.check(lib().qmc_job_set_graph(self.h, int(enable)))
+
+    def set_variant(self, variant):
+        """Run every kernel class with occupancy build `variant` (0 or 1)."""
+        self.plan.ctx.check(lib().qmc_job_set_variant(self.h, int(variant)))
 
     def profile(self, enable=True):
         """Time every kernel-class launch of later eager runs."""

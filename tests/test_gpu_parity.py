@@ -12,6 +12,7 @@ from gpu_util import (assert_assembly_matches, compare_sectors, ctx, gpu_plan,
 from oracle import qmc as oq
 from oracle.decompose import decompose as odec
 from paper_1508_02512_amd import frontend as fe
+from paper_1508_02512_amd import qmc
 from seeded_inputs.lattice import lattice
 from seeded_inputs.problems import PROBLEMS
 from seeded_inputs.rng import shift_table
@@ -206,6 +207,44 @@ def test_double_box_benchmark_config_sampled():
         gpu = res["sector_sums"][0, s, :1]
         scale = abss[..., 0] + abss[..., 1]
         assert np.all(np.abs(gpu - sums) <= 1e-12 * scale), s
+    plan.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_both_occupancy_builds_match_oracle(variant):
+    """Each real kernel class in both occupancy builds (the autotuner picks
+    between them; the one-wave-fewer FP64 builds of three and four poles
+    form the subset constants C(Y), L(Y) once per point): sampled double
+    box sectors of every pole count against the oracle (binary128 from two
+    poles), n = 10007, 2 shifts, 1e-12 of sum |w g|."""
+    print(f"doublebox both builds: variant {variant}", flush=True)
+    plan, info = gpu_plan("doublebox")
+    kin_vals = {"s": -3.0, "t": -1.0}
+    n = 10007
+    z = lattice(n)
+    sh = shift_table(4, 2, 8)
+    job = plan.bind(fe.kin_vector(info, kin_vals), (n, z), sh)
+    job.set_variant(variant)
+    job.run()
+    res = job.fetch(sector_sums=True)
+    job.profile(True)
+    job.run()
+    job.fetch()
+    assert all(c["variant"] == variant for c in job.class_stats())
+    job.close()
+    osecs, oinfo = odec(PROBLEMS["doublebox"])
+    for s in sample_sectors("doublebox", per_class=2):
+        ns = oq.NumericSector(osecs[s], oinfo, kin_vals)
+        sums, abss, _ = oq.sector_sums(ns, n, z, sh, 2, 0.0, res["sec_lo"],
+                                       plan.info.sec_orders, quad=ns.nJ >= 2)
+        scale = abss[..., 0] + abss[..., 1]
+        assert np.all(np.abs(res["sector_sums"][0, s] - sums) <= 1e-12 * scale), (s, ns.nJ)
+    with pytest.raises(qmc.QMCError):
+        job2 = plan.bind(fe.kin_vector(info, kin_vals), (n, z), sh)
+        try:
+            job2.set_variant(2)
+        finally:
+            job2.close()
     plan.close()
 
 
