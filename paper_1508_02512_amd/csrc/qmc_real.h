@@ -627,9 +627,9 @@ __attribute__((amdgpu_waves_per_eu(min_waves<KS, T, V>(), 8))) void qmc_eval_rea
     __shared__ double st[lds_state_slots<KS, K, T>() * QMC_BLOCK];
     pw[(QMC_PROG_SLOTS - 1) * QMC_BLOCK + threadIdx.x] = T(1);
     for (int item = A.item_begin + (int)blockIdx.x; item < A.item_end; item += (int)gridDim.x) {
-        // the one-wave-fewer FP64 builds of three and four poles have
-        // registers to spare for the subset constants
-        constexpr bool PRE = sizeof(T) == 8 && V == 1 && KS >= 3;
+        // FP64: the subset constants once per point (in FP32, C(Y) alone
+        // can overflow, so there each factor is folded into h^[Y])
+        constexpr bool PRE = sizeof(T) == 8 && KS >= 1;
         qmc_eval_real_item<KS, K, T, NUM, PRE>(A, item, pw + threadIdx.x, st + threadIdx.x);
         __syncthreads();
     }
