@@ -278,7 +278,10 @@ void qmc_job_free(qmc_job *job);
  * should have the lattice sizes of the production runs; two shifts are
  * enough) and remembers, per (plan, poles, kernel width, lattice-size
  * octave), the fastest points per lane (the length of each lane's point
- * loop), persistent-grid setting and occupancy build (waves per SIMD).  Later
+ * loop), persistent-grid setting and occupancy build (waves per SIMD); a
+ * shape later in the order of preference (points per lane 64, 16, 256, 4,
+ * 1024; then build 0, 1; then grid off, 4, 8 per CU) must be more than 2%
+ * faster to replace an earlier one, so noise does not flip choices.  Later
  * binds with points_per_lane = 0 use them.  choices (may be NULL) receives
  * up to max_choices entries; *n_choices is set to the number of classes. */
 typedef struct {

@@ -1369,9 +1369,13 @@ extern "C" int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *ki
                             qmc_tune_choice *choices, int32_t max_choices, int32_t *n_choices)
 {
     if (!ctx || !plan) return QMC_EINVAL;
-    static const int ppls[] = {4, 16, 64, 256, 1024};
+    // candidates in order of preference; a later one replaces the best so
+    // far only when it is more than 2% faster, so that shapes whose times
+    // differ by noise do not flip from one tuning to the next
+    static const int ppls[] = {64, 16, 256, 4, 1024};
     static const int grids[] = {0, 4, 8};
     static const int variants[] = {0, 1};
+    constexpr float margin = 0.98f;
     std::map<std::string, std::pair<qmc_tune, std::pair<int, int>>> best;
     for (int ppl : ppls) {
         qmc_job *job = nullptr;
@@ -1406,7 +1410,7 @@ extern "C" int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *ki
                     continue;
                 const std::string key = qmc_tune_key(plan, c.ks, c.dm, c.num, nmax);
                 auto it = best.find(key);
-                if (it == best.end() || ms < it->second.first.ms) {
+                if (it == best.end() || ms < margin * it->second.first.ms) {
                     qmc_tune t;
                     t.ppl = ppl;
                     t.grid_per_cu = gpc;
