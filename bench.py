@@ -685,8 +685,8 @@ def main():
         "config": {"workload": "planar double box (7 props, 6 dims), Euclidean "
                                "s=-3 t=-1, all sectors, eps^-4..eps^0, Korobov r=2",
                    "sectors": plan.n_sectors, "lattice_n": n, "shifts": m,
-                   "evals_per_step": evals_per_step, "precision": "fp64",
-                   "autotune": tuned},
+                   "evals_per_step": evals_per_step, "precision": "fp64"},
+        "launch_shapes": tuned,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
                      "traffic": traffic, "traffic_source": traffic_src,

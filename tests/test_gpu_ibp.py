@@ -64,6 +64,11 @@ def test_sector_sums_match_oracle(name, kin, eps_hi):
     compare_sectors(name, kin, 10007, 3, eps_hi=eps_hi)
 
 
+def test_geometric_sectors_match_oracle():
+    print("ibp parity: sunset_dot123, geometric sectors", flush=True)
+    compare_sectors("sunset_dot123", {"s": -2.0}, 10007, 3, strategy="geometric")
+
+
 def test_sector_sums_many_tiles_and_persistent_points_per_lane():
     print("ibp parity: box_dot, ppl 3", flush=True)
     compare_sectors("box_dot", {"s": -3.0, "t": -2.0}, 100003, 2, ppl=3)

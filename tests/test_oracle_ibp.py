@@ -20,6 +20,7 @@ import pytest
 
 from oracle import ibp, qmc
 from oracle.decompose import decompose
+from oracle.geometric import decompose as geometric
 from seeded_inputs.lattice import lattice
 from seeded_inputs.problems import PROBLEMS
 from seeded_inputs.rng import shift_table
@@ -206,3 +207,15 @@ def test_dotted_bubble_expansion_by_hand():
     # 2 eps/(1 + eps) = 2 eps - 2 eps^2 + ...
     assert der["C"].get(0, 0) == 0
     assert all(der["C"][k] == 2 * (-1) ** (k + 1) for k in range(1, ibp.NSER))
+
+
+def test_geometric_sectors_with_integration_by_parts():
+    """The geometric decomposition also leaves powers below -1 (here -2 in
+    the sunset with powers (1, 2, 3)); Eq. 13 on its sectors reproduces the
+    closed form as well."""
+    secs, info = geometric(PROBLEMS["sunset_dot123"])
+    assert min(a for s in secs for a in s["a"]) == -2
+    n = 10007
+    res = qmc.integrate(None, {"s": -2.0}, n, lattice(n), shift_table(0, 8, 8), eps_hi=1,
+                        sectors=(secs, info))
+    _check(res, _laurent(_sunset(1, 2, 3, -2.0), -2, 1))
