@@ -13,7 +13,10 @@ the derivative of the rest of the integrand:
 
 and it is applied again while the power stays below -1.  When it reaches
 -1 exactly the remaining pole is the one Eq. 11 subtracts; a power between
--2 and -1 ends above -1 and needs nothing more.
+-2 and -1 ends above -1 and needs nothing more.  Applied also at -1 (the
+paper's alternative to the subtraction), 1/(alpha + 1 + beta eps) becomes
+1/(beta eps) and the sector comes out without a pole, its coefficient
+series starting at eps^-1.
 
 Here f = C(eps) * P_1 ... P_r * U^(u0 + u1 eps) * F^(f0 + f1 eps) times the
 monomials of the other variables, with numerator factors P_i (polynomials
@@ -84,6 +87,7 @@ def _at_one(poly, j):
 
 
 def _ser_mul(x, y):
+    """Product of two Laurent series, orders below NSER kept."""
     out = {}
     for p, a in x.items():
         for q, b in y.items():
@@ -93,7 +97,10 @@ def _ser_mul(x, y):
 
 
 def _ser_inv_linear(c0, c1):
-    """1/(c0 + c1 eps) for c0 != 0 as a power series."""
+    """1/(c0 + c1 eps) as a Laurent series: a power series for c0 != 0,
+    1/(c1 eps) for c0 = 0 (an exponent -1 taken by Eq. 13)."""
+    if c0 == 0:
+        return {-1: 1 / c1}
     r = -c1 / c0
     return {k: (r ** k) / c0 for k in range(NSER) if r ** k != 0 or k == 0}
 
@@ -146,12 +153,17 @@ def _step(sec, j):
     return out
 
 
-def _expand_var(sec, j):
-    if j in sec["fixed"] or sec["a"][j] >= -1:
+def _expand_var(sec, j, poles):
+    """Eq. 13 in variable j while its power is below -1, or (poles) while
+    it is -1 or below."""
+    a = sec["a"][j]
+    if j in sec["fixed"] or a > -1 or (a == -1 and not poles):
         return [sec]
+    if a == -1 and sec["b"][j] == 0:
+        raise ValueError("a = -1 with b = 0: the pole is not regulated")
     out = []
     for t in _step(sec, j):
-        out.extend(_expand_var(t, j))
+        out.extend(_expand_var(t, j, poles))
     return out
 
 
@@ -174,16 +186,19 @@ def _compact(sec, origin):
             "u": sec["u"], "f": sec["f"], "C": sec["C"], "origin": origin}
 
 
-def needs_ibp(sectors):
-    return any(a < -1 for s in sectors for a in s["a"])
+def needs_ibp(sectors, poles=False):
+    return any(a < -1 or (poles and a == -1) for s in sectors for a in s["a"])
 
 
-def expand(sectors, info):
-    """Every sector with some a_j < -1 replaced by its Eq. 13 expansion.
+def expand(sectors, info, poles=False):
+    """Every sector with some a_j < -1 replaced by its Eq. 13 expansion;
+    with poles=True also every a_j = -1 (Eq. 13 as the alternative to the
+    subtraction of Eq. 11: the sectors come out without poles, and their
+    coefficient series C start at eps^-p, p the number of poles taken).
 
     Each output sector carries its own powers u = (u0, u1), f = (f0, f1),
-    numerator factors P, coefficient series C (times the input sector's D)
-    and the index of the input sector it came from."""
+    numerator factors P, coefficient series C (a Laurent series, times the
+    input sector's D) and the index of the input sector it came from."""
     out = []
     for idx, s in enumerate(sectors):
         d = len(s["a"])
@@ -195,7 +210,7 @@ def expand(sectors, info):
         for j in range(d):
             nxt = []
             for t in secs:
-                nxt.extend(_expand_var(t, j))
+                nxt.extend(_expand_var(t, j, poles))
             secs = nxt
         out.extend(_compact(t, idx) for t in secs)
     return out

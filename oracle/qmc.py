@@ -217,27 +217,34 @@ def gamma_prefactor(info, lo, hi):
     return out, -pole
 
 
-def assemble(per_sector, D, pref, pref_lo, sec_lo, n, eps_lo, eps_hi):
+def assemble(per_sector, D, pref, pref_lo, sec_lo, n, eps_lo, eps_hi, tot_lo=None):
     """Per-shift Laurent estimates, mean and error (Eqs. 18-20).
 
     per_sector: list of arrays [m][K] complex of raw sums (no 1/n), orders
-    sec_lo.. ; D: list of sector constants, each a number or a power series
-    {order >= 0: coefficient} in eps (the coefficient C(eps) of a sector
-    from Eq. 13); pref: dict order->coeff.
+    sec_lo.. ; D: list of sector constants, each a number or a Laurent
+    series {order: coefficient} in eps (the coefficient C(eps) of a sector
+    from Eq. 13); pref: dict order->coeff.  The sum over sectors of C(eps)
+    times the sector's series is kept from order tot_lo (default sec_lo;
+    lower when some C(eps) starts below eps^0) up to eps_hi - pref_lo.
     """
     m = per_sector[0].shape[0]
     K = per_sector[0].shape[1]
-    tot = np.zeros((m, K), dtype=complex)
+    if tot_lo is None:
+        tot_lo = sec_lo
+    Kt = eps_hi - pref_lo - tot_lo + 1
+    tot = np.zeros((m, Kt), dtype=complex)
     for S, Ds in zip(per_sector, D):
         ser = Ds if isinstance(Ds, dict) else {0: Ds}
         for e, c in ser.items():
-            if 0 <= e < K:
-                tot[:, e:] += complex(c) * S[:, :K - e] / float(n)
+            for i in range(K):
+                j = sec_lo + i + e - tot_lo
+                if 0 <= j < Kt:
+                    tot[:, j] += complex(c) * S[:, i] / float(n)
     orders = list(range(eps_lo, eps_hi + 1))
     Q = np.zeros((m, len(orders)), dtype=complex)
     for qi, p in enumerate(orders):
-        for j in range(K):
-            ps = sec_lo + j
+        for j in range(Kt):
+            ps = tot_lo + j
             pp = p - ps
             if pp in pref:
                 Q[:, qi] += pref[pp] * tot[:, j]
@@ -249,19 +256,28 @@ def assemble(per_sector, D, pref, pref_lo, sec_lo, n, eps_lo, eps_hi):
 
 
 def integrate(problem, kin, n, z, shifts, r=2, lam=0.0, eps_hi=0, nthreads=0,
-              sectors=None, quad=False):
-    """Whole-problem oracle estimate: dict with orders, mean, errors."""
+              sectors=None, quad=False, poles="subtract"):
+    """Whole-problem oracle estimate: dict with orders, mean, errors.
+
+    poles="subtract" takes the poles a_j = -1 out by the subtraction of
+    Eq. 11 (integration by parts only below -1); poles="ibp" takes them out
+    by the integration by parts of Eq. 13 as well."""
+    if poles not in ("subtract", "ibp"):
+        raise ValueError(f"unknown pole method {poles!r}")
     if sectors is None:
         sectors, info = decompose(problem)
     else:
         sectors, info = sectors
-    if ibp.needs_ibp(sectors):
-        sectors = ibp.expand(sectors, info)
+    by_parts = poles == "ibp"
+    if ibp.needs_ibp(sectors, by_parts):
+        sectors = ibp.expand(sectors, info, by_parts)
     nums = [NumericSector(s, info, kin) for s in sectors]
     kmax = max(ns.nJ for ns in nums)
-    pref_probe, pref_lo = gamma_prefactor(info, -2, eps_hi + kmax + 2)
+    # lowest order of the coefficient series C(eps) (below 0 after Eq. 13 at -1)
+    c_lo = min([0] + [min(s["C"]) for s in sectors if "C" in s and s["C"]])
+    pref_probe, pref_lo = gamma_prefactor(info, -2, eps_hi + kmax - c_lo + 2)
     sec_lo = -kmax
-    sec_hi = eps_hi - pref_lo
+    sec_hi = eps_hi - pref_lo - c_lo
     K = sec_hi - sec_lo + 1
     per = []
     counts = np.zeros(3, dtype=np.int64)
@@ -270,9 +286,9 @@ def integrate(problem, kin, n, z, shifts, r=2, lam=0.0, eps_hi=0, nthreads=0,
                               nthreads, quad)
         per.append(S)
         counts += c.sum(axis=0)
-    eps_lo = sec_lo + pref_lo
+    eps_lo = sec_lo + c_lo + pref_lo
     res = assemble(per, [s["C"] if "C" in s else float(s.get("D", 1)) for s in sectors],
-                   pref_probe, pref_lo, sec_lo, n, eps_lo, eps_hi)
+                   pref_probe, pref_lo, sec_lo, n, eps_lo, eps_hi, sec_lo + c_lo)
     res["sector_sums"] = per
     res["counts"] = counts
     res["sec_lo"] = sec_lo
