@@ -64,6 +64,10 @@ extern "C" {
 #define QMC_MAX_FACTORS 4        /* numerator factors per sector after Eq. 13 */
 #define QMC_MAX_EXP 15           /* largest exponent of a polynomial term */
 
+/* ---- pole methods (qmc_plan_opts.pole_method) ---------------------------- */
+#define QMC_POLES_SUBTRACT 0     /* poles a_j = -1 subtracted (Eq. 11) */
+#define QMC_POLES_IBP 1          /* poles a_j = -1 integrated by parts (Eq. 13) as well */
+
 /* ---- precision modes ----------------------------------------------------- */
 #define QMC_FP64 0               /* all arithmetic in FP64 */
 #define QMC_FP32_EVAL 1          /* FP32 integrand, FP64 where stability needs it */
@@ -91,11 +95,13 @@ typedef struct {
 } qmc_poly;
 
 /* One sector (Eq. 9): D * prod_j t_j^(a_j + b_j eps) U^(u0 + u1 eps) F^(f0 + f1 eps).
- * a_j = -1 (then b_j != 0): the pole is subtracted (Eq. 11).  a_j < -1 (as
+ * a_j = -1 (then b_j != 0): the pole is subtracted (Eq. 11), or, with
+ * pole_method QMC_POLES_IBP, integrated by parts (Eq. 13).  a_j < -1 (as
  * dotted propagators give): the plan applies the integration by parts of
- * Eq. 13 in that variable until its power is -1 or above -1, which turns
- * the sector into several, with numerator factors (derivatives of U and F)
- * and an eps-dependent coefficient each; Euclidean plans only (lambda = 0).
+ * Eq. 13 in that variable until its power is -1 or above -1 (with
+ * QMC_POLES_IBP: above -1), which turns the sector into several, with
+ * numerator factors (derivatives of U and F) and an eps-dependent
+ * coefficient each; Euclidean plans only (lambda = 0).
  * U and F must contain the all-zero exponent (their constant term). */
 typedef struct {
     int32_t dim;                 /* 1 .. QMC_MAX_DIM */
@@ -123,6 +129,7 @@ typedef struct {
     int32_t korobov_r;           /* periodiser order 0..3 (Eq. 21 is r = 1) */
     double lambda;               /* deformation parameter; 0 = Euclidean */
     int32_t points_per_lane;     /* 0 = chosen by the library */
+    int32_t pole_method;         /* QMC_POLES_SUBTRACT or QMC_POLES_IBP */
 } qmc_plan_opts;
 
 /* Rank-1 lattice (Eq. 17): points {i z / n}, i = 0 .. n-1; 2 <= n < 2^31,
@@ -154,14 +161,18 @@ typedef struct {
  * increasing index, each application of Eq. 13 giving the boundary term,
  * then the derivative terms (numerator factors in order, then U, then F),
  * each expanded completely before the next.  A sector without exponents
- * below -1 is planned unchanged (C = D, no factor). */
+ * below -1 (with QMC_POLES_IBP: without exponents <= -1) is planned
+ * unchanged (C = D, no factor).  With QMC_POLES_IBP every pole a_j = -1
+ * contributes 1/(b_j eps) to C, so C starts at eps^-p (p poles taken) and
+ * the planned sector has no pole left. */
 typedef struct {
     int32_t origin;              /* index of the input sector */
     int32_t dim;                 /* integration variables */
     int32_t poles;               /* variables with a_j = -1 (Eq. 11) */
     int32_t factors;             /* numerator factors r */
     double u_exp[2], f_exp[2];   /* powers of U and F */
-    double coef[QMC_MAX_ORDERS][2];   /* C(eps) = sum_k coef[k] eps^k (re, im) */
+    double coef[QMC_MAX_ORDERS][2];   /* C(eps) = sum_k coef[k] eps^(coef_lo + k) (re, im) */
+    int32_t coef_lo;             /* 0, or -QMC_MAX_POLES with QMC_POLES_IBP */
 } qmc_sector_info;
 
 typedef struct {
@@ -190,7 +201,7 @@ int qmc_set_stream(qmc_ctx *ctx, void *hip_stream);
 const char *qmc_last_error(qmc_ctx *ctx);
 
 /* Plan the sectors of Eq. 9 (Section II): validate them, apply Eq. 13
- * where some a_j < -1, permute each
+ * where some a_j < -1 (with QMC_POLES_IBP: a_j <= -1), permute each
  * sector's variables so the subtracted ones come first, sort polynomial
  * terms by which of those they contain, derive dF and d2F tables when
  * lambda > 0, and upload the tables.  Everything sized "per sector" below

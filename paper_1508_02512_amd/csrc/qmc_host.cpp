@@ -230,8 +230,10 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
     if (pb->eps_hi < pb->eps_lo) return set_err(ctx, QMC_EINVAL, "eps_hi < eps_lo");
     if (pb->n_pref < 1 || !pb->prefactor)
         return set_err(ctx, QMC_EINVAL, "prefactor series is empty");
-    qmc_plan_opts o = {QMC_FP64, 2, 0.0, 0};
+    qmc_plan_opts o = {QMC_FP64, 2, 0.0, 0, QMC_POLES_SUBTRACT};
     if (opts) o = *opts;
+    if (o.pole_method != QMC_POLES_SUBTRACT && o.pole_method != QMC_POLES_IBP)
+        return set_err(ctx, QMC_EINVAL, "unknown pole method %d", o.pole_method);
     if (o.korobov_r < 0 || o.korobov_r > 3)
         return set_err(ctx, QMC_EUNSUPPORTED, "korobov_r must be 0..3");
     if (o.precision != QMC_FP64 && o.precision != QMC_FP32_EVAL)
@@ -283,7 +285,7 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
     std::vector<qmc_ibp_sec> xs;
     {
         char msg[256] = {};
-        const int rc = qmc_ibp_expand(pb, xs, msg, sizeof msg);
+        const int rc = qmc_ibp_expand(pb, o.pole_method == QMC_POLES_IBP, xs, msg, sizeof msg);
         if (rc != QMC_OK) {
             delete plan;
             return set_err(ctx, rc, "%s", msg);
@@ -291,15 +293,16 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
     }
     plan->n_input_sectors = pb->n_sectors;
     const int ns = (int)xs.size();
-    int max_ks = 0;
+    int max_ks = 0, cmin = 0;
     // pass 1: poles and numerator factors per sector
     for (int s = 0; s < ns; ++s) {
         const qmc_ibp_sec &X = xs[s];
         if (X.ibp && o.lambda > 0.0) {
             delete plan;
             return set_err(ctx, QMC_EUNSUPPORTED,
-                           "sector %d: integration by parts (exponent below -1) is supported "
-                           "for Euclidean plans only (lambda = 0)", X.origin);
+                           "sector %d: integration by parts (%s) is supported for Euclidean "
+                           "plans only (lambda = 0)", X.origin,
+                           o.pole_method == QMC_POLES_IBP ? "pole method" : "exponent below -1");
         }
         if ((int)X.eP.size() > QMC_MAX_FACTORS) {
             delete plan;
@@ -324,16 +327,28 @@ extern "C" int qmc_plan_sectors(qmc_ctx *ctx, const qmc_problem *pb,
                            QMC_MAX_POLES);
         }
         max_ks = std::max(max_ks, ks);
+        for (size_t e = 0; e < X.C.size(); ++e)
+            if (X.C[e] != 0.0) {
+                cmin = std::min(cmin, X.clo + (int)e);
+                break;
+            }
     }
-    plan->sec_lo = -max_ks;
-    plan->sec_hi = pb->eps_hi - pb->eps_pref_lo;
-    const int kb = plan->sec_hi + 1;
-    if (kb < 1 || kb > 3) {
+    // orders: the sum over sectors of C(eps) times the sector's series runs
+    // over tot_lo .. tot_hi; a sector with ks poles carries -ks .. tot_hi - cmin
+    plan->tot_hi = pb->eps_hi - pb->eps_pref_lo;
+    const int kout = plan->tot_hi + 1;
+    if (kout < 1 || kout > 3) {
         delete plan;
         return set_err(ctx, QMC_EUNSUPPORTED,
-                       "sector orders above the poles (%d) must be 1..3", kb);
+                       "sector orders above the poles (%d) must be 1..3", kout);
     }
-    if (plan->sec_hi - plan->sec_lo + 1 > QMC_MAX_ORDERS) {
+    const int kb = kout - cmin;
+    plan->c_lo = xs.empty() ? 0 : xs[0].clo;
+    plan->tot_lo = -max_ks + cmin;
+    plan->sec_lo = -max_ks;
+    plan->sec_hi = plan->tot_hi - cmin;
+    if (plan->sec_hi - plan->sec_lo + 1 > QMC_MAX_ORDERS ||
+        plan->tot_hi - plan->tot_lo + 1 > QMC_MAX_ORDERS) {
         delete plan;
         return set_err(ctx, QMC_EUNSUPPORTED, "too many Laurent orders");
     }
@@ -673,6 +688,7 @@ extern "C" int qmc_plan_sector_info(const qmc_plan *plan, int32_t s, qmc_sector_
         out->coef[e][0] = h.C[e].real();
         out->coef[e][1] = h.C[e].imag();
     }
+    out->coef_lo = plan->c_lo;
     return QMC_OK;
 }
 
@@ -857,7 +873,7 @@ int qmc_job_prepare(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32
         for (int s = 0; s < ns; ++s) {
             const int dm = qmc_sector_mode(plan, s, coef.data() + (size_t)p * nt,
                                            &lam[(size_t)p * ns + s]);
-            const std::array<int, 3> key{plan->secs[s].ks, dm, plan->secs[s].nf > 0 ? 1 : 0};
+            const std::array<int, 3> key{plan->secs[s].ks, dm, qmc_num_class(plan, s)};
             auto it = std::find(keys.begin(), keys.end(), key);
             if (it == keys.end()) {
                 keys.push_back(key);
@@ -1081,7 +1097,7 @@ int qmc_assemble(const qmc_plan *plan, int n_points, int m, const std::vector<ui
                  const double *gsum /* [groups][kstride][2] */, qmc_result *out)
 {
     const int ns = (int)plan->secs.size();
-    const int K = plan->sec_hi - plan->sec_lo + 1;
+    const int K = plan->tot_hi - plan->tot_lo + 1;
     const int no = plan->eps_hi - plan->eps_lo + 1;
     std::vector<std::complex<double>> tot(K), Q((size_t)m * no);
     for (int p = 0; p < n_points; ++p) {
@@ -1095,9 +1111,9 @@ int qmc_assemble(const qmc_plan *plan, int n_points, int m, const std::vector<ui
                     const std::complex<double> v(g[2 * q], g[2 * q + 1]);
                     // the sector's coefficient series C(eps) (D, or Eq. 13's)
                     for (size_t e = 0; e < h.C.size(); ++e) {
-                        const int j = order + (int)e - plan->sec_lo;
+                        const int j = order + plan->c_lo + (int)e - plan->tot_lo;
                         if (j >= K) break;
-                        if (h.C[e] != 0.0) tot[j] += h.C[e] * v / (double)nsec[s];
+                        if (j >= 0 && h.C[e] != 0.0) tot[j] += h.C[e] * v / (double)nsec[s];
                     }
                 }
             }
@@ -1105,7 +1121,7 @@ int qmc_assemble(const qmc_plan *plan, int n_points, int m, const std::vector<ui
                 const int order = plan->eps_lo + oi;
                 std::complex<double> acc = 0.0;
                 for (int j = 0; j < K; ++j) {
-                    const int pp = order - (plan->sec_lo + j) - plan->eps_pref_lo;
+                    const int pp = order - (plan->tot_lo + j) - plan->eps_pref_lo;
                     if (pp < 0 || pp >= plan->n_pref) continue;
                     acc += std::complex<double>(plan->pref[2 * pp], plan->pref[2 * pp + 1]) * tot[j];
                 }

@@ -5,7 +5,10 @@
 //   int t^(alpha+beta eps) f dt = f(1)/(alpha+1+beta eps)
 //                                 - 1/(alpha+1+beta eps) int t^(alpha+1+beta eps) df/dt dt
 // until its exponent is -1 (then the subtraction of Eq. 11 takes over) or
-// above -1.  f = C(eps) P_1 .. P_r U^(u0+u1 eps) F^(f0+f1 eps) (times the
+// above -1.  In the pole mode (the paper's alternative to the subtraction)
+// it is applied at -1 as well: 1/(alpha+1+beta eps) is then 1/(beta eps),
+// and the sector comes out without a pole, its series C starting at
+// eps^-1 per pole taken.  f = C(eps) P_1 .. P_r U^(u0+u1 eps) F^(f0+f1 eps) (times the
 // other variables' monomials) stays of that form: by the product rule
 // every term of df/dt either replaces a numerator factor P_i by dP_i/dt,
 // or appends dU/dt (resp. dF/dt) as a factor, lowers the power of U
@@ -47,11 +50,18 @@ struct wsec {
     wpoly U, F;
     std::vector<wpoly> P;            // numerator factors
     double u0 = 0, u1 = 0, f0 = 0, f1 = 0;
-    std::vector<cd> C;               // coefficient series eps^0 .. QMC_MAX_ORDERS-1
+    std::vector<cd> C;               // coefficient series eps^clo .. eps^(clo+NSER-1)
 };
+
+// Orders kept while expanding: every 1/(b eps) of Eq. 13 at a pole leaves
+// the top order of the window incomplete, so QMC_MAX_POLES orders beyond
+// the QMC_MAX_ORDERS handed out keep those exact.
+constexpr int NSER = QMC_MAX_ORDERS + QMC_MAX_POLES;
 
 struct ctx_t {
     int d = 0, ni = 0;
+    bool poles = false;              // Eq. 13 at a = -1 too
+    int clo = 0;                     // lowest order of the C window
     size_t produced = 0;
     char *err = nullptr;
     size_t errlen = 0;
@@ -100,12 +110,18 @@ wpoly at_one(const wpoly &p, int j, int ni)
     return out;
 }
 
-std::vector<cd> ser_mul(const std::vector<cd> &x, const std::vector<cd> &y)
+// x in the C window times y = y[0] eps^ylo + y[1] eps^(ylo+1) + ..., kept in
+// the window (orders above it dropped; nothing falls below it, as the
+// expansion bounds the poles that Eq. 13 takes to the window's depth).
+std::vector<cd> ser_mul(const std::vector<cd> &x, const std::vector<cd> &y, int ylo)
 {
-    std::vector<cd> r(QMC_MAX_ORDERS, 0.0);
-    for (size_t p = 0; p < x.size(); ++p)
-        for (size_t q = 0; q < y.size() && p + q < (size_t)QMC_MAX_ORDERS; ++q)
-            r[p + q] += x[p] * y[q];
+    std::vector<cd> r(NSER, 0.0);
+    for (int p = 0; p < (int)x.size(); ++p)
+        for (int q = 0; q < (int)y.size(); ++q) {
+            const int i = p + q + ylo;
+            if (i >= NSER) break;
+            if (i >= 0) r[i] += x[p] * y[q];
+        }
     return r;
 }
 
@@ -116,12 +132,18 @@ bool ser_zero(const std::vector<cd> &x)
     return true;
 }
 
-// 1/(c0 + c1 eps) = (1/c0) sum_k (-c1/c0)^k eps^k
-std::vector<cd> ser_inv_linear(double c0, double c1)
+// 1/(c0 + c1 eps) = (1/c0) sum_k (-c1/c0)^k eps^k for c0 != 0, from eps^0;
+// 1/(c1 eps) for c0 = 0, from eps^-1 (ylo of the result)
+std::vector<cd> ser_inv_linear(double c0, double c1, int &ylo)
 {
-    std::vector<cd> r(QMC_MAX_ORDERS, 0.0);
+    if (c0 == 0.0) {
+        ylo = -1;
+        return {1.0 / c1};
+    }
+    ylo = 0;
+    std::vector<cd> r(NSER, 0.0);
     double v = 1.0 / c0;
-    for (int k = 0; k < QMC_MAX_ORDERS; ++k) {
+    for (int k = 0; k < NSER; ++k) {
         r[k] = v;
         v *= -c1 / c0;
     }
@@ -131,7 +153,8 @@ std::vector<cd> ser_inv_linear(double c0, double c1)
 std::vector<wsec> ibp_step(const wsec &s, int j, const ctx_t &C)
 {
     const double alpha = s.a[j], beta = s.b[j];
-    const std::vector<cd> inv = ser_inv_linear(alpha + 1.0, beta);
+    int ilo = 0;
+    const std::vector<cd> inv = ser_inv_linear(alpha + 1.0, beta, ilo);
     std::vector<wsec> out;
     {   // boundary term
         wsec t = s;
@@ -143,14 +166,14 @@ std::vector<wsec> ibp_step(const wsec &s, int j, const ctx_t &C)
             p = at_one(p, j, C.ni);
             vanished |= p.e.empty();
         }
-        t.C = ser_mul(s.C, inv);
+        t.C = ser_mul(s.C, inv, ilo);
         if (!vanished && !ser_zero(t.C)) out.push_back(std::move(t));
     }
     std::vector<cd> minv(inv.size());
     for (size_t k = 0; k < inv.size(); ++k) minv[k] = -inv[k];
     wsec base = s;
     base.a[j] = alpha + 1.0;
-    base.C = ser_mul(s.C, minv);
+    base.C = ser_mul(s.C, minv, ilo);
     for (size_t i = 0; i < s.P.size(); ++i) {
         wpoly dp = deriv(s.P[i], j, C.ni);
         if (dp.e.empty()) continue;
@@ -167,7 +190,7 @@ std::vector<wsec> ibp_step(const wsec &s, int j, const ctx_t &C)
         t.P.push_back(std::move(dq));
         if (which == 0) t.u0 -= 1.0;
         else t.f0 -= 1.0;
-        t.C = ser_mul(base.C, std::vector<cd>{e0, e1});
+        t.C = ser_mul(base.C, std::vector<cd>{e0, e1}, 0);
         if (!ser_zero(t.C)) out.push_back(std::move(t));
     }
     return out;
@@ -175,7 +198,7 @@ std::vector<wsec> ibp_step(const wsec &s, int j, const ctx_t &C)
 
 bool expand_var(const wsec &s, int j, ctx_t &C, std::vector<wsec> &out)
 {
-    if ((s.fixed >> j & 1u) || s.a[j] >= -1.0) {
+    if ((s.fixed >> j & 1u) || s.a[j] > -1.0 || (s.a[j] == -1.0 && !C.poles)) {
         if (++C.produced > MAX_EXPANDED) return false;
         out.push_back(s);
         return true;
@@ -199,8 +222,8 @@ void flatten(const wpoly &p, const std::vector<int> &keep, int ni, std::vector<u
 
 } // namespace
 
-int qmc_ibp_expand(const qmc_problem *pb, std::vector<qmc_ibp_sec> &out, char *err,
-                   size_t errlen)
+int qmc_ibp_expand(const qmc_problem *pb, bool poles, std::vector<qmc_ibp_sec> &out,
+                   char *err, size_t errlen)
 {
     out.clear();
     const int ni = pb->n_inv;
@@ -210,6 +233,27 @@ int qmc_ibp_expand(const qmc_problem *pb, std::vector<qmc_ibp_sec> &out, char *e
         ctx_t C;
         C.d = d;
         C.ni = ni;
+        C.poles = poles;
+        C.clo = poles ? -QMC_MAX_POLES : 0;
+        if (poles) {
+            // each variable with an integer power <= -1 passes -1 once, and
+            // Eq. 13 there divides by b eps: at most QMC_MAX_POLES of them
+            int np = 0;
+            for (int j = 0; j < d; ++j) {
+                const double a = S.mono_a[j];
+                if (a > -1.0 || a != std::floor(a)) continue;
+                if (S.mono_b[j] == 0.0) {
+                    snprintf(err, errlen, "sector %d var %d: a = %g, b = 0: the pole is not "
+                                          "regulated", s, j, a);
+                    return QMC_EUNREGULATED;
+                }
+                ++np;
+            }
+            if (np > QMC_MAX_POLES) {
+                snprintf(err, errlen, "sector %d: %d poles > %d", s, np, QMC_MAX_POLES);
+                return QMC_EUNSUPPORTED;
+            }
+        }
         wsec w;
         for (int j = 0; j < d; ++j) {
             w.a[j] = S.mono_a[j];
@@ -229,10 +273,10 @@ int qmc_ibp_expand(const qmc_problem *pb, std::vector<qmc_ibp_sec> &out, char *e
         w.u1 = S.u_exp[1];
         w.f0 = S.f_exp[0];
         w.f1 = S.f_exp[1];
-        w.C.assign(QMC_MAX_ORDERS, 0.0);
-        w.C[0] = cd(S.coef_re, S.coef_im);
+        w.C.assign(NSER, 0.0);
+        w.C[-C.clo] = cd(S.coef_re, S.coef_im);
         bool any = false;
-        for (int j = 0; j < d; ++j) any |= w.a[j] < -1.0;
+        for (int j = 0; j < d; ++j) any |= w.a[j] < -1.0 || (poles && w.a[j] == -1.0);
         std::vector<wsec> cur{w};
         for (int j = 0; j < d && any; ++j) {
             std::vector<wsec> nxt;
@@ -267,7 +311,8 @@ int qmc_ibp_expand(const qmc_problem *pb, std::vector<qmc_ibp_sec> &out, char *e
             x.u1 = t.u1;
             x.f0 = t.f0;
             x.f1 = t.f1;
-            x.C = t.C;
+            x.C.assign(t.C.begin(), t.C.begin() + QMC_MAX_ORDERS);
+            x.clo = C.clo;
             out.push_back(std::move(x));
         }
     }

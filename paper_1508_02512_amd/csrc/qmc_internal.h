@@ -53,20 +53,22 @@ struct qmc_ctx {
 struct qmc_ibp_sec {
     int origin = 0;                  // index of the input sector
     int dim = 0;
-    bool ibp = false;                // the input sector had some a_j < -1
+    bool ibp = false;                // Eq. 13 was applied to the input sector
     std::vector<double> a, b;
     std::vector<uint8_t> eU, eF;
     std::vector<double> cU, cF;
     std::vector<std::vector<uint8_t>> eP;
     std::vector<std::vector<double>> cP;
     double u0 = 0, u1 = 0, f0 = 0, f1 = 0;
-    std::vector<std::complex<double>> C;
+    std::vector<std::complex<double>> C;  // C[e]: coefficient of eps^(clo + e)
+    int clo = 0;
 };
 
-// Every sector of the problem expanded by Eq. 13 where needed, in the
-// documented order.  Returns QMC_OK or an error code with a message in err.
-int qmc_ibp_expand(const qmc_problem *pb, std::vector<qmc_ibp_sec> &out, char *err,
-                   size_t errlen);
+// Every sector of the problem expanded by Eq. 13 where needed (powers below
+// -1; with `poles`, powers -1 as well), in the documented order.  Returns
+// QMC_OK or an error code with a message in err.
+int qmc_ibp_expand(const qmc_problem *pb, bool poles, std::vector<qmc_ibp_sec> &out,
+                   char *err, size_t errlen);
 
 // One sector as planned: permuted exponents, term ranges, flop count.
 struct qmc_sec_host {
@@ -87,7 +89,7 @@ struct qmc_sec_host {
     int nf = 0;                      // numerator factors (Eq. 13)
     int32_t pm[QMC_NFMAX][QMC_NMASK + 1] = {};
     int32_t pm1[QMC_NFMAX][QMC_NMASK] = {}, pm2[QMC_NFMAX][QMC_NMASK] = {};
-    std::vector<std::complex<double>> C{1.0};   // coefficient series, eps^0 ..
+    std::vector<std::complex<double>> C{1.0};   // coefficient series, eps^c_lo ..
     std::vector<int> term_nnz;   // non-zero exponents per term (U and F)
     std::vector<int> dterm_nnz;  // the same for the derivative terms
     double flops = 0.0;          // algorithmic flops per lattice point
@@ -103,6 +105,8 @@ struct qmc_plan {
     int eps_lo = 0, eps_hi = 0, eps_pref_lo = 0, n_pref = 0;
     std::vector<double> pref;        // [n_pref][2]
     int sec_lo = 0, sec_hi = 0;      // sector orders carried
+    int tot_lo = 0, tot_hi = 0;      // orders of sum_s C_s(eps) I_s(eps)
+    int c_lo = 0;                    // order of C[0] in every sector's series C
     int kb = 1;                      // orders from eps^0 up: sec_hi + 1
     int kstride = 1;                 // order slots per group: kb + max_ks
     int max_ks = 0;
@@ -122,6 +126,15 @@ struct qmc_plan {
     uint32_t *d_dprog = nullptr;
     uint32_t *d_dexp = nullptr;
 };
+
+// Kernel build of sector s: 1 = with numerator factors (Eq. 13).  The
+// builds without them carry at most 3 orders above the poles; wider
+// sectors (Eq. 13 taken at the poles) use the numerator build, where no
+// factor is a product of 1.
+inline int qmc_num_class(const qmc_plan *P, int s)
+{
+    return P->secs[s].nf > 0 || P->kb > 3 ? 1 : 0;
+}
 
 // largest grid of one launch: (2^32 - 1) work-items / QMC_BLOCK lanes
 constexpr int QMC_MAX_GRID = (int)(0xffffffffu / QMC_BLOCK);

@@ -9,7 +9,8 @@
 // Laurent orders, evaluated in FP64 or FP32; one work-group per item in
 // [item_begin, item_end).  variant 0 is the build with the swept occupancy,
 // variant 1 the build with one wave per SIMD fewer (less spilling).  num:
-// the sectors carry numerator factors (Eq. 13; variant 0 only).
+// the sectors carry numerator factors (Eq. 13; variant 0 only); only these
+// builds go beyond kb = 3, to kb = 7 for sectors without poles.
 hipError_t qmc_launch_real(int ks, int kb, bool fp32, int variant, bool num,
                            const qmc_launch_args &args, int grid, hipStream_t stream);
 
@@ -37,10 +38,12 @@ hipError_t qmc_launch_serve_accumulate(const double *partial, const int32_t *vio
                                        double *const *dst, const int32_t *gks, int n_groups,
                                        int kstride, int32_t *gviol, hipStream_t stream);
 // Serving: a request's sums [ns][m][kstride][4] combined over sectors per
-// shift and sector order, each sector's series times its coefficient series
-// D[ns][QMC_NCOEF][2]: tot[m][n_orders][2].
+// shift and order, each sector's series times its coefficient series
+// D[ns][QMC_NCOEF][2]: tot[m][n_orders][2].  Order j of tot takes slot
+// q = j - e + q_base + ks of a sector with ks poles for D's entry e
+// (q_base: lowest order of tot minus the order of D's entry 0).
 hipError_t qmc_launch_serve_combine(const double *sums, const qmc_sec_dev *sec, const double *D,
-                                    int ns, int m, int kstride, int n_orders, int sec_lo,
+                                    int ns, int m, int kstride, int n_orders, int q_base,
                                     double inv_n, double *tot, hipStream_t stream);
 // p[0..n) = v.
 hipError_t qmc_launch_fill(double *p, long n, double v, hipStream_t stream);

@@ -20,6 +20,7 @@ QMC_REAL_LAUNCHER(qmc_launch_real_f32_v1)
 QMC_REAL_LAUNCHER(qmc_launch_real_num_lo)
 QMC_REAL_LAUNCHER(qmc_launch_real_num_hi)
 QMC_REAL_LAUNCHER(qmc_launch_real_num_f32)
+QMC_REAL_LAUNCHER(qmc_launch_real_num_wide)
 
 hipError_t qmc_launch_real(int ks, int kb, bool fp32, int variant, bool num,
                            const qmc_launch_args &args, int grid, hipStream_t stream)
@@ -27,6 +28,7 @@ hipError_t qmc_launch_real(int ks, int kb, bool fp32, int variant, bool num,
     if (grid <= 0) return hipSuccess;
     if (num) {   // one occupancy build: these classes are small
         if (fp32) return qmc_launch_real_num_f32(ks, kb, args, grid, stream);
+        if (kb > 3) return qmc_launch_real_num_wide(ks, kb, args, grid, stream);
         return ks <= 2 ? qmc_launch_real_num_lo(ks, kb, args, grid, stream)
                        : qmc_launch_real_num_hi(ks, kb, args, grid, stream);
     }
@@ -160,19 +162,20 @@ hipError_t qmc_launch_serve_accumulate(const double *partial, const int32_t *vio
 // each sum compensated, sectors in index order.  One thread per (k, j).
 __global__ void qmc_serve_combine_k(const double *sums, const qmc_sec_dev *sec,
                                     const double *D, int ns, int m, int kstride, int n_orders,
-                                    int sec_lo, double inv_n, double *tot)
+                                    int q_base, double inv_n, double *tot)
 {
     const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (tid >= m * n_orders) return;
     const int k = tid / n_orders, j = tid % n_orders;
     double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
     for (int s = 0; s < ns; ++s) {
-        // order j of the sector's series times C(eps): sum_e C_e v_{j-e}
+        // order j of the sum times C(eps): sum_e C_e v_{j-e}, with the
+        // orders of the total, of C and of the sector's slots offset by q_base
         for (int e = 0; e < QMC_NCOEF; ++e) {
             const double dr = D[2 * (s * QMC_NCOEF + e)];
             const double di = D[2 * (s * QMC_NCOEF + e) + 1];
             if (dr == 0.0 && di == 0.0) continue;
-            const int q = j - e + sec_lo + sec[s].ks;
+            const int q = j - e + q_base + sec[s].ks;
             if (q < 0 || q >= sec[s].K) continue;
             const double *p = sums + (((size_t)s * m + k) * kstride + q) * 4;
             const double vr = (p[0] + p[1]) * inv_n, vi = (p[2] + p[3]) * inv_n;
@@ -188,7 +191,7 @@ __global__ void qmc_serve_combine_k(const double *sums, const qmc_sec_dev *sec,
 }
 
 hipError_t qmc_launch_serve_combine(const double *sums, const qmc_sec_dev *sec, const double *D,
-                                    int ns, int m, int kstride, int n_orders, int sec_lo,
+                                    int ns, int m, int kstride, int n_orders, int q_base,
                                     double inv_n, double *tot, hipStream_t stream)
 {
     const int total = m * n_orders;
@@ -196,7 +199,7 @@ hipError_t qmc_launch_serve_combine(const double *sums, const qmc_sec_dev *sec, 
     const int threads = 64;
     hipLaunchKernelGGL(qmc_serve_combine_k, dim3((total + threads - 1) / threads),
                        dim3(threads), 0, stream, sums, sec, D, ns, m, kstride, n_orders,
-                       sec_lo, inv_n, tot);
+                       q_base, inv_n, tot);
     return hipGetLastError();
 }
 

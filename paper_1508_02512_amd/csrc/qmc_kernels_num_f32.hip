@@ -7,5 +7,6 @@ hipError_t qmc_launch_real_num_f32(int ks, int kb, const qmc_launch_args &args, 
 {
     QMC_REAL_CASES_LO(float, 0, true)
     QMC_REAL_CASES_HI(float, 0, true)
+    QMC_REAL_CASES_WIDE(float, 0, true)
     return hipErrorInvalidValue;
 }

@@ -649,6 +649,12 @@ __attribute__((amdgpu_waves_per_eu(min_waves<KS, T, V>(), 8))) void qmc_eval_rea
     QMC_REAL_CASE(1, 1, T, V, NUM) QMC_REAL_CASE(1, 2, T, V, NUM) QMC_REAL_CASE(1, 3, T, V, NUM) \
     QMC_REAL_CASE(2, 1, T, V, NUM) QMC_REAL_CASE(2, 2, T, V, NUM) QMC_REAL_CASE(2, 3, T, V, NUM)
 
+// pole-free sectors carrying 4-7 orders (integration by parts taken at the
+// poles: the orders the poles would have held move above eps^0)
+#define QMC_REAL_CASES_WIDE(T, V, NUM)                                                         \
+    QMC_REAL_CASE(0, 4, T, V, NUM) QMC_REAL_CASE(0, 5, T, V, NUM) QMC_REAL_CASE(0, 6, T, V, NUM) \
+    QMC_REAL_CASE(0, 7, T, V, NUM)
+
 #define QMC_REAL_CASES_HI(T, V, NUM)                                                           \
     QMC_REAL_CASE(3, 1, T, V, NUM) QMC_REAL_CASE(3, 2, T, V, NUM) QMC_REAL_CASE(3, 3, T, V, NUM) \
     QMC_REAL_CASE(4, 1, T, V, NUM) QMC_REAL_CASE(4, 2, T, V, NUM) QMC_REAL_CASE(4, 3, T, V, NUM)

@@ -204,7 +204,7 @@ size_t request_bytes(const qmc_plan *P, int m, uint64_t n0, uint64_t n_max)
     // step buffers grow by a quarter beyond what they hold
     const size_t step = items * (sizeof(qmc_item) + (size_t)QMC_MAX_ORDERS * 32 + 4) +
                         items * (4 + 4 + 8 + 4 + 4) +          // group ranges, destinations
-                        (size_t)m * ks * 16;                   // combined totals
+                        (size_t)m * (P->tot_hi - P->tot_lo + 1) * 16;   // combined totals
     return groups * ks * 32 + step * 5 / 4 + 3 * 4096;
 }
 
@@ -231,11 +231,11 @@ bool converged(const Request *r)
 }
 
 // Per-shift Laurent series (prefactor times the combined sector sums), then
-// mean and error over the shifts (Eqs. 19-20).  tot: [m][sector orders][2].
+// mean and error over the shifts (Eqs. 19-20).  tot: [m][orders tot_lo..tot_hi][2].
 void assemble_totals(const qmc_plan *P, int m, const std::vector<double> &tot,
                      std::vector<qmc_coeff> &coeff)
 {
-    const int K = P->sec_hi - P->sec_lo + 1;
+    const int K = P->tot_hi - P->tot_lo + 1;
     const int no = P->eps_hi - P->eps_lo + 1;
     std::vector<std::complex<double>> Q((size_t)m * no);
     for (int k = 0; k < m; ++k)
@@ -243,7 +243,7 @@ void assemble_totals(const qmc_plan *P, int m, const std::vector<double> &tot,
             const int order = P->eps_lo + oi;
             std::complex<double> acc = 0.0;
             for (int j = 0; j < K; ++j) {
-                const int pp = order - (P->sec_lo + j) - P->eps_pref_lo;
+                const int pp = order - (P->tot_lo + j) - P->eps_pref_lo;
                 if (pp < 0 || pp >= P->n_pref) continue;
                 const std::complex<double> v(tot[((size_t)k * K + j) * 2],
                                              tot[((size_t)k * K + j) * 2 + 1]);
@@ -454,7 +454,7 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act, std::vector<Reques
         for (const Win &w : wins) {
             if (w.r->plan != P) continue;
             for (int s = 0; s < ns; ++s) {
-                std::array<int, 3> key{P->secs[s].ks, w.r->dm[s], P->secs[s].nf > 0 ? 1 : 0};
+                std::array<int, 3> key{P->secs[s].ks, w.r->dm[s], qmc_num_class(P, s)};
                 if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
             }
         }
@@ -474,8 +474,7 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act, std::vector<Reques
                 const uint64_t g0 = w.begin / ipg, g1 = (w.end - 1) / ipg;
                 for (uint64_t g = g0; g <= g1; ++g) {
                     const int s = (int)(g / r->m), k = (int)(g % r->m);
-                    if (P->secs[s].ks != c.ks || r->dm[s] != c.dm ||
-                        (P->secs[s].nf > 0 ? 1 : 0) != c.num)
+                    if (P->secs[s].ks != c.ks || r->dm[s] != c.dm || qmc_num_class(P, s) != c.num)
                         continue;
                     gbeg.push_back((int32_t)items.size());
                     const uint64_t i0 = std::max(w.begin, g * ipg), i1 = std::min(w.end, (g + 1) * ipg);
@@ -570,7 +569,7 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act, std::vector<Reques
     for (size_t i = 0; i < done_lv.size() && e == hipSuccess; ++i) {
         Request *r = done_lv[i];
         const qmc_plan *P = r->plan;
-        const int K = P->sec_hi - P->sec_lo + 1;
+        const int K = P->tot_hi - P->tot_lo + 1;
         void *d_tot;
         char name[32];
         snprintf(name, sizeof name, "tot%zu", i);
@@ -580,7 +579,8 @@ int run_step(qmc_serve_state *S, std::vector<Request *> &act, std::vector<Reques
         }
         e = qmc_launch_serve_combine((const double *)r->sums.p, P->d_sec,
                                      (const double *)S->pools[P].D.p, (int)P->secs.size(), r->m,
-                                     P->kstride, K, P->sec_lo, 1.0 / (double)r->level_n,
+                                     P->kstride, K, P->tot_lo - P->c_lo,
+                                     1.0 / (double)r->level_n,
                                      (double *)d_tot, st);
         tots[i].resize((size_t)r->m * K * 2);
         if (e == hipSuccess)

@@ -23,6 +23,8 @@ ERRORS = {-1: "QMC_EINVAL", -2: "QMC_EUNREGULATED", -3: "QMC_EUNSUPPORTED",
 (QMC_EINVAL, QMC_EUNREGULATED, QMC_EUNSUPPORTED, QMC_ENOMEM, QMC_EBUDGET, QMC_EDEFORM,
  QMC_ENOTCONVERGED, QMC_EDEVICE, QMC_ECANCELLED) = range(-1, -10, -1)
 QMC_FP64, QMC_FP32_EVAL = 0, 1
+QMC_POLES_SUBTRACT, QMC_POLES_IBP = 0, 1
+QMC_MAX_POLES = 4
 QMC_MATH_LN, QMC_MATH_LN1P, QMC_MATH_EXP, QMC_MATH_EXPM1, QMC_MATH_RCP = 0, 1, 2, 3, 4
 QMC_MAX_DIM = 8
 QMC_MAX_ORDERS = 8
@@ -50,7 +52,7 @@ class qmc_problem(C.Structure):
 
 class qmc_plan_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("korobov_r", C.c_int32), ("lambda_", C.c_double),
-                ("points_per_lane", C.c_int32)]
+                ("points_per_lane", C.c_int32), ("pole_method", C.c_int32)]
 
 
 class qmc_lattice(C.Structure):
@@ -73,7 +75,7 @@ class qmc_plan_info(C.Structure):
 class qmc_sector_info(C.Structure):
     _fields_ = [("origin", C.c_int32), ("dim", C.c_int32), ("poles", C.c_int32),
                 ("factors", C.c_int32), ("u_exp", C.c_double * 2), ("f_exp", C.c_double * 2),
-                ("coef", (C.c_double * 2) * QMC_MAX_ORDERS)]
+                ("coef", (C.c_double * 2) * QMC_MAX_ORDERS), ("coef_lo", C.c_int32)]
 
 
 class qmc_result(C.Structure):
@@ -209,16 +211,16 @@ class Context:
             pass
 
     def plan(self, sectors, info, eps_hi, prefactor, lam=0.0, korobov_r=2,
-             precision=QMC_FP64, points_per_lane=0, D=None):
+             precision=QMC_FP64, points_per_lane=0, D=None, pole_method=QMC_POLES_SUBTRACT):
         return Plan(self, sectors, info, eps_hi, prefactor, lam, korobov_r, precision,
-                    points_per_lane, D)
+                    points_per_lane, D, pole_method)
 
 
 class Plan:
     """Sector tables planned and resident on the device."""
 
     def __init__(self, ctx, sectors, info, eps_hi, prefactor, lam, korobov_r, precision,
-                 points_per_lane, D):
+                 points_per_lane, D, pole_method=QMC_POLES_SUBTRACT):
         self.ctx = ctx
         self.keep = []
         ns = len(sectors)
@@ -258,7 +260,7 @@ class Plan:
         max_poles = max(int(np.sum((s["a"] <= -1.0) & (s["a"] == np.floor(s["a"]))))
                         for s in sectors)
         prob.eps_lo = -max_poles + pref_lo
-        opts = qmc_plan_opts(precision, korobov_r, float(lam), points_per_lane)
+        opts = qmc_plan_opts(precision, korobov_r, float(lam), points_per_lane, pole_method)
         self.h = C.c_void_p()
         ctx.check(lib().qmc_plan_sectors(ctx.h, C.byref(prob), C.byref(opts),
                                          C.byref(self.h)))
@@ -268,14 +270,15 @@ class Plan:
         self.n_sectors = self.info.n_sectors      # after Eq. 13
 
     def sector_info(self, s):
-        """Planned sector s: origin, dim, poles, factors, u, f and the
-        coefficient series C(eps) (complex array, eps^0 ..)."""
+        """Planned sector s: origin, dim, poles, factors, u, f, the
+        coefficient series C(eps) (complex array, orders C_lo ..) and C_lo."""
         out = qmc_sector_info()
         self.ctx.check(lib().qmc_plan_sector_info(self.h, int(s), C.byref(out)))
         return {"origin": out.origin, "dim": out.dim, "poles": out.poles,
                 "factors": out.factors, "u": tuple(out.u_exp), "f": tuple(out.f_exp),
                 "C": np.array([complex(out.coef[k][0], out.coef[k][1])
-                               for k in range(QMC_MAX_ORDERS)])}
+                               for k in range(QMC_MAX_ORDERS)]),
+                "C_lo": out.coef_lo}
 
     def close(self):
         if self.h:

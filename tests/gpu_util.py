@@ -25,12 +25,13 @@ def ctx():
     return _CTX
 
 
-def oracle_sectors(name, strategy="iterated"):
+def oracle_sectors(name, strategy="iterated", poles=False):
     """The oracle's sectors of a problem, after its own integration by parts
-    (Eq. 13) where some a_j < -1: one to one with the planned sectors."""
+    (Eq. 13) where some a_j < -1 (poles=True: a_j <= -1): one to one with
+    the planned sectors."""
     secs, info = (ogeo if strategy == "geometric" else odec)(PROBLEMS[name])
-    if ibp.needs_ibp(secs):
-        secs = ibp.expand(secs, info)
+    if ibp.needs_ibp(secs, poles):
+        secs = ibp.expand(secs, info, poles)
     return secs, info
 
 
@@ -40,11 +41,12 @@ def sector_coef(s):
 
 
 def gpu_plan(name, eps_hi=0, lam=0.0, r=2, ppl=0, precision=qmc.QMC_FP64,
-             strategy="iterated"):
+             strategy="iterated", poles=False):
     secs, info = fe.decompose(PROBLEMS[name], strategy)
     plan = ctx().plan(fe.sector_arrays(secs, info), info, eps_hi,
                       fe.prefactor_series(info, 12), lam=lam, korobov_r=r,
-                      points_per_lane=ppl, precision=precision)
+                      points_per_lane=ppl, precision=precision,
+                      pole_method=qmc.QMC_POLES_IBP if poles else qmc.QMC_POLES_SUBTRACT)
     return plan, info
 
 
@@ -65,17 +67,17 @@ def sample_sectors(name, per_class=8, kin=None, strategy="iterated"):
 
 def compare_sectors(name, kin, n, m, eps_hi=0, lam=0.0, r=2, ppl=0, tol=1e-12,
                     sectors=None, seed=0, quad_from=2, precision=qmc.QMC_FP64,
-                    strategy="iterated", kind="korobov"):
+                    strategy="iterated", kind="korobov", poles=False):
     """Max over (sector, shift, order) of |gpu - oracle| / sum|terms|.
 
     Sectors with at least `quad_from` poles are compared with the oracle's
     binary128 build: the mixed differences of Eq. 11 amplify the FP64
     oracle's own rounding beyond the parity bar there."""
-    plan, info = gpu_plan(name, eps_hi, lam, r, ppl, precision, strategy)
+    plan, info = gpu_plan(name, eps_hi, lam, r, ppl, precision, strategy, poles)
     z = lattice(n, kind)
     shifts = shift_table(seed, m, 8)
     res = plan.integrate(fe.kin_vector(info, kin), (n, z), shifts, sector_sums=True)
-    osecs, oinfo = oracle_sectors(name, strategy)
+    osecs, oinfo = oracle_sectors(name, strategy, poles)
     idx = range(len(osecs)) if sectors is None else sectors
     worst = 0.0
     for s in idx:
@@ -94,17 +96,19 @@ def compare_sectors(name, kin, n, m, eps_hi=0, lam=0.0, r=2, ppl=0, tol=1e-12,
 
 
 def oracle_assembled(name, kin, n, z, shifts, eps_hi=0, lam=0.0, r=2, strategy="iterated",
-                     quad_from=2):
+                     quad_from=2, poles=False):
     """The oracle's whole-problem result (Eqs. 19-20) on the given lattice and
     shifts, with sectors of at least `quad_from` poles summed in binary128,
     and a rounding scale per order: the largest over shifts of the same
     assembly taken over |prefactor|, |D| and sum_i |w g|."""
-    osecs, oinfo = oracle_sectors(name, strategy)
+    osecs, oinfo = oracle_sectors(name, strategy, poles)
     nums = [oq.NumericSector(s, oinfo, kin) for s in osecs]
     kmax = max(ns.nJ for ns in nums)
-    pref, pref_lo = oq.gamma_prefactor(oinfo, -2, eps_hi + kmax + 2)
+    # lowest order of the coefficient series (below 0 after Eq. 13 at poles)
+    c_lo = min([0] + [min(s["C"]) for s in osecs if "C" in s and s["C"]])
+    pref, pref_lo = oq.gamma_prefactor(oinfo, -2, eps_hi + kmax - c_lo + 2)
     sec_lo = -kmax
-    K = eps_hi - pref_lo - sec_lo + 1
+    K = eps_hi - pref_lo - c_lo - sec_lo + 1
     per, per_abs = [], []
     for ns in nums:
         sums, abss, _ = oq.sector_sums(ns, n, z, shifts, r, oq.effective_lambda(ns, lam),
@@ -113,10 +117,10 @@ def oracle_assembled(name, kin, n, z, shifts, eps_hi=0, lam=0.0, r=2, strategy="
         per_abs.append((abss[..., 0] + abss[..., 1]).astype(complex))
     D = [sector_coef(s) for s in osecs]
     Dabs = [{k: abs(v) for k, v in d.items()} if isinstance(d, dict) else abs(d) for d in D]
-    eps_lo = sec_lo + pref_lo
-    res = oq.assemble(per, D, pref, pref_lo, sec_lo, n, eps_lo, eps_hi)
+    eps_lo = sec_lo + c_lo + pref_lo
+    res = oq.assemble(per, D, pref, pref_lo, sec_lo, n, eps_lo, eps_hi, sec_lo + c_lo)
     absres = oq.assemble(per_abs, Dabs, {k: abs(v) for k, v in pref.items()},
-                         pref_lo, sec_lo, n, eps_lo, eps_hi)
+                         pref_lo, sec_lo, n, eps_lo, eps_hi, sec_lo + c_lo)
     res["scale"] = np.max(np.abs(absres["per_shift"]), axis=0)
     return res
 

@@ -63,7 +63,8 @@ def test_binding_structs_match_header_layout(tmp_path):
 
 def test_limits_match_binding():
     text = open(os.path.join(ROOT, "include", "qmc.h")).read()
-    for name in ("QMC_MAX_DIM", "QMC_MAX_ORDERS", "QMC_MAX_FACTORS"):
+    for name in ("QMC_MAX_DIM", "QMC_MAX_ORDERS", "QMC_MAX_FACTORS", "QMC_MAX_POLES",
+                 "QMC_POLES_SUBTRACT", "QMC_POLES_IBP"):
         m = re.search(rf"#define {name} (\d+)", text)
         assert m and int(m.group(1)) == getattr(qmc, name), name
 
