@@ -138,6 +138,8 @@ def parse():
     ap.add_argument("--no-time-to-target", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-pole-methods", action="store_true",
+                    help="skip the double box with its poles integrated by parts")
     ap.add_argument("--no-autotune", action="store_true",
                     help="bind the main workload with the library's default launch shapes")
     ap.add_argument("--no-workloads", action="store_true",
@@ -651,6 +653,45 @@ def main():
         plan32.close()
         log(f"fp32: {fp32['value']:.3e} evals/s")
 
+    # the poles integrated by parts (Eq. 13) instead of subtracted (Eq. 11):
+    # time to 1e-3, and the FP32-evaluation deviation from FP64 in units of
+    # the Eq. 20 error for both pole methods on one lattice
+    poles_ibp = None
+    if not args.no_pole_methods:
+        tp = time.perf_counter()
+        pl_i = ctx.plan(arrs, info, 0, fe.prefactor_series(info, 12),
+                        pole_method=qmc.QMC_POLES_IBP)
+        poles_ibp = {"sectors": pl_i.n_sectors, "host_planning_seconds":
+                     time.perf_counter() - tp,
+                     "flops_per_point": pl_i.info.flops_per_point,
+                     "flops_per_point_subtraction": plan.info.flops_per_point}
+        if not args.no_autotune:
+            pl_i.autotune(kin, (131071, lattice(131071)), shift_table(0, 4, 8))
+        if not args.no_time_to_target:
+            poles_ibp["time_to_1e-3"], _ = time_to_target(pl_i, "fp64, poles by parts")
+        nb = 131071
+        dev = {}
+        for label, pm in (("subtraction", qmc.QMC_POLES_SUBTRACT),
+                          ("by_parts", qmc.QMC_POLES_IBP)):
+            r = {}
+            for prec in (qmc.QMC_FP64, qmc.QMC_FP32_EVAL):
+                pq = pl_i if (pm, prec) == (qmc.QMC_POLES_IBP, qmc.QMC_FP64) else ctx.plan(
+                    arrs, info, 0, fe.prefactor_series(info, 12), precision=prec,
+                    pole_method=pm)
+                r[prec] = pq.integrate(kin, (nb, lattice(nb)), shift_table(0, m, 8))
+                if pq is not pl_i:
+                    pq.close()
+            a, b = r[qmc.QMC_FP64], r[qmc.QMC_FP32_EVAL]
+            sig = np.hypot(a["err_re"][0], a["err_im"][0])
+            dev[label] = {"evals_per_s_fp64": a["evals"] / (a["kernel_ms"] / 1e3),
+                          "max_rel_err_fp64": max_rel_err(a),
+                          "fp32_dev_in_sigma_per_order":
+                              [float(x) for x in np.abs(b["mean"][0] - a["mean"][0]) / sig]}
+        poles_ibp["fp32_vs_fp64_at_n"] = nb
+        poles_ibp["methods"] = dev
+        pl_i.close()
+        log(f"poles by parts: {poles_ibp}")
+
     workloads = None
     if not args.no_workloads:
         workloads = {
@@ -710,6 +751,7 @@ def main():
         "time_to_1e-3_cbc_vectors": ttt_cbc,
         "time_to_1e-3_geometric_sectors": ttt_geo,
         "fp32_eval": fp32,
+        "poles_by_parts": poles_ibp,
         "paper_workloads_time_to_1e-3": paper,
         "serve": serve,
         "workloads": workloads,
