@@ -140,6 +140,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-pole-methods", action="store_true",
                     help="skip the double box with its poles integrated by parts")
+    ap.add_argument("--pole-methods-n", type=int, default=131071,
+                    help="lattice size of the FP32/FP64 comparison of both pole methods")
     ap.add_argument("--no-autotune", action="store_true",
                     help="bind the main workload with the library's default launch shapes")
     ap.add_argument("--no-workloads", action="store_true",
@@ -669,7 +671,7 @@ def main():
             pl_i.autotune(kin, (131071, lattice(131071)), shift_table(0, 4, 8))
         if not args.no_time_to_target:
             poles_ibp["time_to_1e-3"], _ = time_to_target(pl_i, "fp64, poles by parts")
-        nb = 131071
+        nb = args.pole_methods_n
         dev = {}
         for label, pm in (("subtraction", qmc.QMC_POLES_SUBTRACT),
                           ("by_parts", qmc.QMC_POLES_IBP)):
@@ -684,7 +686,11 @@ def main():
             a, b = r[qmc.QMC_FP64], r[qmc.QMC_FP32_EVAL]
             sig = np.hypot(a["err_re"][0], a["err_im"][0])
             dev[label] = {"evals_per_s_fp64": a["evals"] / (a["kernel_ms"] / 1e3),
+                          "evals_per_s_fp32": b["evals"] / (b["kernel_ms"] / 1e3),
                           "max_rel_err_fp64": max_rel_err(a),
+                          "fp32_rel_dev_per_order":
+                              [float(x) for x in np.abs(b["mean"][0] - a["mean"][0])
+                               / np.abs(a["mean"][0])],
                           "fp32_dev_in_sigma_per_order":
                               [float(x) for x in np.abs(b["mean"][0] - a["mean"][0]) / sig]}
         poles_ibp["fp32_vs_fp64_at_n"] = nb
