@@ -142,6 +142,8 @@ def parse():
                     help="skip the double box with its poles integrated by parts")
     ap.add_argument("--pole-methods-n", type=int, default=131071,
                     help="lattice size of the FP32/FP64 comparison of both pole methods")
+    ap.add_argument("--pole-methods-ttt", action="store_true",
+                    help="also time the poles-by-parts plan to 1e-3 (about a minute)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="bind the main workload with the library's default launch shapes")
     ap.add_argument("--no-workloads", action="store_true",
@@ -669,7 +671,7 @@ def main():
                      "flops_per_point_subtraction": plan.info.flops_per_point}
         if not args.no_autotune:
             pl_i.autotune(kin, (131071, lattice(131071)), shift_table(0, 4, 8))
-        if not args.no_time_to_target:
+        if args.pole_methods_ttt:
             poles_ibp["time_to_1e-3"], _ = time_to_target(pl_i, "fp64, poles by parts")
         nb = args.pole_methods_n
         dev = {}
