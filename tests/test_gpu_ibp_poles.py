@@ -92,6 +92,13 @@ def test_double_box_sector_sums_match_oracle(precision):
                     precision=precision, tol=tol)
 
 
+@pytest.mark.parametrize("name,kin", [("box", {"s": -3.0, "t": -2.0}),
+                                      ("sunset_dot123", {"s": -2.0})])
+def test_geometric_sectors_match_oracle(name, kin):
+    print(f"ibp poles parity: {name}, geometric sectors", flush=True)
+    compare_sectors(name, kin, 10007, 3, strategy="geometric", poles=True)
+
+
 def test_sector_sums_many_tiles_and_persistent_points_per_lane():
     print("ibp poles parity: box_dot, ppl 3", flush=True)
     compare_sectors("box_dot", {"s": -3.0, "t": -2.0}, 100003, 2, ppl=3, poles=True)

@@ -54,6 +54,21 @@ def test_noalloc_deformed_and_several_points():
     plan.close()
 
 
+def test_noalloc_with_poles_integrated_by_parts():
+    """Plans expanded by Eq. 13 at the poles (pole-free sectors with up to 5
+    orders, numerator factors, Laurent coefficient series): the double box
+    (48798 sectors) then the dotted box, both entry points alike."""
+    print("noalloc: double box and dotted box, poles by parts", flush=True)
+    for name, kin, n, m in (("doublebox", {"s": -3.0, "t": -1.0}, 1009, 2),
+                            ("box_dot", {"s": -3.0, "t": -2.0}, 4099, 3)):
+        plan, info = gpu_plan(name, poles=True)
+        args = (fe.kin_vector(info, kin), (n, lattice(n)), shift_table(1, m, 8))
+        want = plan.integrate(*args, sector_sums=True)
+        got = plan.integrate(*args, sector_sums=True, noalloc=True)
+        _same(want, got)
+        plan.close()
+
+
 def test_noalloc_refuses_more_than_the_scratch_array():
     print("noalloc: oversized call refused", flush=True)
     plan, info = gpu_plan("box")
