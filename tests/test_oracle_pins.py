@@ -201,7 +201,10 @@ def _massive_bubble_eps0(s, m2=1.0):
     raise ValueError
 
 
-def test_bubble_values_in_survey_table():
+def test_bubble_closed_form_values():
+    """eps^0 of the massless bubble (Gamma(eps) normalisation) is
+    2 - gamma_E - ln(-s): 0.3241720464... at s = -3; at s = 3 the branch
+    -i0 adds i pi."""
     ex = _bubble_exact(-3.0, 1)
     assert abs(ex[0] - 0.324172046430357) < 1e-14
     assert abs(ex[1] - 1.23007672441931) < 1e-13
