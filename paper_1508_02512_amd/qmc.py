@@ -212,6 +212,10 @@ class Context:
 
     def plan(self, sectors, info, eps_hi, prefactor, lam=0.0, korobov_r=2,
              precision=QMC_FP64, points_per_lane=0, D=None, pole_method=QMC_POLES_SUBTRACT):
+        """qmc_plan_sectors: sectors as frontend.sector_arrays gives them,
+        results up to eps^eps_hi, prefactor (lowest order, coefficients);
+        lam > 0 deforms the contour; pole_method QMC_POLES_IBP integrates
+        the poles by parts instead of subtracting them."""
         return Plan(self, sectors, info, eps_hi, prefactor, lam, korobov_r, precision,
                     points_per_lane, D, pole_method)
 
