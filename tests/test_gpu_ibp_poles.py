@@ -5,13 +5,15 @@ per (sector, shift, order) against the oracle at 1e-12 of sum |w g| (the
 pole-free sectors carry up to 7 orders: the wide kernel builds), the
 assembled result and Eq. 20 errors against the oracle's, whole results
 against closed forms in FP64 and FP32, both pole methods on the double box,
-serving, and the refusals."""
+several kinematic points with uneven lattices and graph replay, serving,
+and the refusals."""
 
 import numpy as np
 import pytest
 
 from gpu_util import (assert_assembly_matches, compare_sectors, ctx, gpu_plan,
                       oracle_assembled, oracle_sectors)
+from oracle import qmc as oq
 from oracle.decompose import decompose as odec
 from paper_1508_02512_amd import frontend as fe
 from paper_1508_02512_amd import qmc
@@ -167,6 +169,40 @@ def test_double_box_both_pole_methods_agree():
         sig = np.hypot(a["err_re"][0][i], b["err_re"][0][i])
         assert abs(d.real) <= 6 * sig + 1e-12 * abs(a["mean"][0][i]), \
             (p, a["mean"][0][i], b["mean"][0][i], sig)
+
+
+def test_batch_points_uneven_lattices_and_graph():
+    """Pole-method plan of the dotted box at 6 Euclidean points with uneven
+    per-sector lattices in one bind: graph replays give the eager bits, and
+    sampled (point, sector) sums match the oracle at 1e-12."""
+    print("ibp poles batch: box_dot 6 points, uneven lattices", flush=True)
+    plan, info = gpu_plan("box_dot", poles=True)
+    pts = [{"s": -0.5 - 0.7 * i, "t": -2.5 + 0.3 * i} for i in range(6)]
+    kin = np.stack([fe.kin_vector(info, k) for k in pts])
+    sizes = [1009, 4099, 10007]
+    lats = [(n, lattice(n)) for n in (sizes[i % 3] for i in range(plan.n_sectors))]
+    sh = shift_table(6, 3, 8)
+    eager = plan.integrate(kin, None, sh, lat_per_sector=lats, sector_sums=True)
+    job = plan.bind(kin, None, sh, lat_per_sector=lats)
+    job.use_graph(True)
+    for rep in range(3):
+        job.run()
+        got = job.fetch(sector_sums=True)
+        np.testing.assert_array_equal(got["sector_sums"], eager["sector_sums"])
+        plan.integrate(kin[:2], None, sh, lat_per_sector=lats)
+    job.close()
+    osecs, oinfo = oracle_sectors("box_dot", poles=True)
+    rng = np.random.default_rng(2)
+    for p in rng.choice(len(pts), size=3, replace=False):
+        for s in rng.choice(len(osecs), size=6, replace=False):
+            ns = oq.NumericSector(osecs[s], oinfo, pts[p])
+            n, z = lats[s]
+            sums, abss, _ = oq.sector_sums(ns, n, z, sh, 2, 0.0, eager["sec_lo"],
+                                           plan.info.sec_orders)
+            scale = abss[..., 0] + abss[..., 1]
+            err = np.abs(eager["sector_sums"][p, s] - sums)
+            assert np.all(err <= 1e-12 * np.maximum(scale, 1e-300)), (p, s)
+    plan.close()
 
 
 def test_served_request():
