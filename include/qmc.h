@@ -351,12 +351,15 @@ int qmc_autotune(qmc_ctx *ctx, const qmc_plan *plan, const double *kin, int32_t 
  * kernels use for the logarithms of Eq. 9's factors, the monomials of U and
  * F and the eps expansion (fn: QMC_MATH_LN for x > 0, QMC_MATH_LN1P for
  * x > -1, QMC_MATH_EXP and QMC_MATH_EXPM1 for finite x, QMC_MATH_RCP, the
- * reciprocal of the divisions, for normal x) to n doubles x
+ * reciprocal of the divisions, for normal x; the _F32 codes: the float
+ * versions of FP32 evaluation, applied to x rounded to float) to n doubles x
  * (device) and writes y (device, n doubles) on the context stream, then
  * waits for it.  Outside those domains the result is unspecified.  For tests
  * that bound their error.  Errors: QMC_EINVAL (null pointer, n < 0, unknown
  * fn), QMC_EDEVICE. */
-enum { QMC_MATH_LN = 0, QMC_MATH_LN1P = 1, QMC_MATH_EXP = 2, QMC_MATH_EXPM1 = 3, QMC_MATH_RCP = 4 };
+enum { QMC_MATH_LN = 0, QMC_MATH_LN1P = 1, QMC_MATH_EXP = 2, QMC_MATH_EXPM1 = 3, QMC_MATH_RCP = 4,
+       QMC_MATH_LN_F32 = 5, QMC_MATH_LN1P_F32 = 6, QMC_MATH_EXP_F32 = 7,
+       QMC_MATH_EXPM1_F32 = 8 };
 int qmc_math_eval(qmc_ctx *ctx, int32_t fn, const double *x, double *y, int64_t n);
 
 /* ---- serving (continuous batching) ---------------------------------------

@@ -1370,7 +1370,7 @@ extern "C" int qmc_math_eval(qmc_ctx *ctx, int32_t fn, const double *x, double *
                              int64_t n)
 {
     if (!ctx) return QMC_EINVAL;
-    if (n < 0 || fn < QMC_MATH_LN || fn > QMC_MATH_RCP || (n > 0 && (!x || !y)))
+    if (n < 0 || fn < QMC_MATH_LN || fn > QMC_MATH_EXPM1_F32 || (n > 0 && (!x || !y)))
         return set_err(ctx, QMC_EINVAL, "qmc_math_eval: bad argument");
     (void)hipSetDevice(ctx->device);
     HIP_CHECK(ctx, qmc_launch_math(fn, x, y, (long)n, ctx->stream));

@@ -88,13 +88,19 @@ __global__ void qmc_math_kernel(int fn, const double *x, double *y, long n)
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double v = x[i];
+    const float vf = (float)v;
     double r = 0.0;
     switch (fn) {
     case 0: r = qmc_math::ln(v); break;
     case 1: r = qmc_math::ln1p(v); break;
     case 2: r = qmc_math::ex(v); break;
     case 3: r = qmc_math::exm1(v); break;
-    default: r = qmc_math::rcp(v); break;
+    case 4: r = qmc_math::rcp(v); break;
+    // the float overloads of FP32 evaluation, on x rounded to float
+    case 5: r = qmc_math::ln(vf); break;
+    case 6: r = qmc_math::ln1p(vf); break;
+    case 7: r = qmc_math::ex(vf); break;
+    default: r = qmc_math::exm1(vf); break;
     }
     y[i] = r;
 }

@@ -27,8 +27,20 @@
 // The fits come from gen_math_coeffs.py (qmc_math_coeffs.h), which checks
 // each rounded polynomial against its error budget.  Errors are a few
 // units in the last place, checked against the host library on wide
-// samples by the tests.  The float overloads (FP32 evaluation mode) use
-// the device library.
+// samples by the tests.
+//
+// The float overloads (FP32 evaluation mode) build on the hardware base-2
+// logarithm and exponential (v_log_f32, v_exp_f32: within 1 ulp over the
+// normal range, arguments near 1 included, as measured on gfx950):
+//   ln(x):          log2(x) times ln 2 as a head + tail product; subnormal
+//                   x scaled by 2^32 first.
+//   exp(x):         p = x log2(e) as a head + tail product, 2^p_head times
+//                   1 + p_tail ln 2; results below the normal range formed
+//                   as 2^(p + 64) 2^-64 so they round once.
+//   log1p(x):       Goldberg's formulation ln(u) x / (u - 1) with u = 1 + x
+//                   rounded (x itself when u = 1): the rounding of u cancels.
+//   expm1(x):       Kahan's formulation (u - 1) x / ln(u) with u = e^x
+//                   rounded (x itself when u = 1; u - 1 for |x| > 10).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -140,9 +152,57 @@ __device__ __forceinline__ double exm1(double x)
     return __builtin_amdgcn_ldexp(expm1_reduced(r), ki) + (__builtin_amdgcn_ldexp(1.0, ki) - 1.0);
 }
 
-__device__ __forceinline__ float ln(float x) { return logf(x); }
-__device__ __forceinline__ float ln1p(float x) { return log1pf(x); }
-__device__ __forceinline__ float ex(float x) { return expf(x); }
-__device__ __forceinline__ float exm1(float x) { return expm1f(x); }
+constexpr float LN2F_HI = 0x1.62e430p-1f;       // ln 2 = LN2F_HI + LN2F_LO
+constexpr float LN2F_LO = -0x1.05c610p-29f;
+constexpr float LOG2EF_HI = 0x1.715476p+0f;     // log2(e) = LOG2EF_HI + LOG2EF_LO
+constexpr float LOG2EF_LO = 0x1.4ae0c0p-26f;
+
+// 1 / x: the hardware estimate and one Newton step
+__device__ __forceinline__ float rcp(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// natural logarithm of x >= 0 (0 gives -inf)
+__device__ __forceinline__ float ln(float x)
+{
+    const bool sub = x < 0x1p-126f;
+    float l = __builtin_amdgcn_logf(sub ? x * 0x1p32f : x);
+    l = sub ? l - 32.0f : l;
+    const float h = l * LN2F_HI;
+    return h + fmaf(l, LN2F_LO, fmaf(l, LN2F_HI, -h));
+}
+
+// ln(1 + x) for x >= -1
+__device__ __forceinline__ float ln1p(float x)
+{
+    const float u = 1.0f + x;
+    const float d = u - 1.0f;
+    const float r = ln(u) * (x * rcp(d));
+    return d == 0.0f ? x : r;
+}
+
+// e^x (0 below the subnormal range, inf above the float range)
+__device__ __forceinline__ float ex(float x)
+{
+    x = fminf(fmaxf(x, -150.0f), 100.0f);
+    const float p = x * LOG2EF_HI;
+    const float e = fmaf(x, LOG2EF_LO, fmaf(x, LOG2EF_HI, -p));
+    const bool sub = p < -126.0f;
+    float r = __builtin_amdgcn_exp2f(sub ? p + 64.0f : p);
+    r = fmaf(r, e * LN2F_HI, r);
+    return sub ? r * 0x1p-64f : r;
+}
+
+// e^x - 1
+__device__ __forceinline__ float exm1(float x)
+{
+    const float u = ex(x);
+    const float d = u - 1.0f;
+    if (!(fabsf(x) <= 10.0f)) return d;
+    const float r = d * (x * rcp(ln(u)));
+    return u == 1.0f ? x : r;
+}
 
 } // namespace qmc_math

@@ -26,6 +26,7 @@ QMC_FP64, QMC_FP32_EVAL = 0, 1
 QMC_POLES_SUBTRACT, QMC_POLES_IBP = 0, 1
 QMC_MAX_POLES = 4
 QMC_MATH_LN, QMC_MATH_LN1P, QMC_MATH_EXP, QMC_MATH_EXPM1, QMC_MATH_RCP = 0, 1, 2, 3, 4
+QMC_MATH_LN_F32, QMC_MATH_LN1P_F32, QMC_MATH_EXP_F32, QMC_MATH_EXPM1_F32 = 5, 6, 7, 8
 QMC_MAX_DIM = 8
 QMC_MAX_ORDERS = 8
 QMC_MAX_FACTORS = 4
