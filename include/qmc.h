@@ -77,7 +77,7 @@ extern "C" {
  * FP32, the Jacobian determinant and the logarithms/powers of U and F in
  * FP64; lattice points, corner differences and all sums in FP64.  The
  * Eq. 20 error does not include the FP32 rounding bias (measured up to
- * 2.7e-6 relative on the double box); serving requests on FP32_EVAL plans
+ * 3.2e-6 relative on the double box); serving requests on FP32_EVAL plans
  * must ask for rel_err_target >= QMC_FP32_TARGET_FLOOR. */
 #define QMC_FP32_TARGET_FLOOR 1e-5
 
