@@ -658,8 +658,8 @@ def main():
         log(f"fp32: {fp32['value']:.3e} evals/s")
 
     # the poles integrated by parts (Eq. 13) instead of subtracted (Eq. 11):
-    # time to 1e-3, and the FP32-evaluation deviation from FP64 in units of
-    # the Eq. 20 error for both pole methods on one lattice
+    # rates, errors and the FP32-evaluation deviation from FP64 of both pole
+    # methods on one lattice (the by-parts time to 1e-3 on request)
     poles_ibp = None
     if not args.no_pole_methods:
         tp = time.perf_counter()
