@@ -164,7 +164,7 @@ __device__ __forceinline__ float rcp(float x)
     return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
-// natural logarithm of x >= 0 (0 gives -inf)
+// natural logarithm of a positive finite x
 __device__ __forceinline__ float ln(float x)
 {
     const bool sub = x < 0x1p-126f;
@@ -174,7 +174,7 @@ __device__ __forceinline__ float ln(float x)
     return h + fmaf(l, LN2F_LO, fmaf(l, LN2F_HI, -h));
 }
 
-// ln(1 + x) for x >= -1
+// ln(1 + x) for x > -1
 __device__ __forceinline__ float ln1p(float x)
 {
     const float u = 1.0f + x;
